@@ -1,0 +1,988 @@
+/*
+ * Plain FP64 CPU oracle of the soft-sphere DEM time step.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.  It shares no
+ * code with the GPU library.  Compiled with -ffp-contract=off so that every
+ * expression is evaluated exactly as written (no fused multiply-add).
+ *
+ * Source of every formula: Golshan et al., "Lethe-DEM: an open-source parallel
+ * discrete element solver with load balancing" (arXiv 2106.09576).
+ *   Sec. 2, Eqs. (main1)-(main2)   Newton-Euler equations of motion
+ *   Sec. 2.1, Eq. (deltan)         normal overlap
+ *   Sec. 2.1, Eq. (vecn)           contact normal, from i to j
+ *   Sec. 2.1, Eq. (delta_t)        tangential overlap history update
+ *   Sec. 2.1, Eq. (vrt) and the two equations after it: relative velocities
+ *   Sec. 2.1, Eqs. (normal_force), (tangential_force): spring-dashpot laws
+ *   Sec. 2.1, Eqs. (nonlinearkn)-(nonlinearetat) and the table of effective
+ *             parameters: Hertz-Mindlin coefficients
+ *   Sec. 2.1, Eq. (torque_t)       tangential torque
+ *   Sec. 2.1, table of rolling models, first row: constant rolling torque
+ *   Sec. 2.1, Eqs. (coulomb_overlap)-(coulomb_overlap3): Coulomb limit with
+ *             truncation of the tangential overlap
+ *   Sec. 2.1, last paragraph       particle-wall contacts use the same law
+ *   Sec. 2.2, Eqs. (integ_EE), (halfstep), (newvv): explicit Euler and
+ *             velocity Verlet
+ *   Sec. 3.2                       broad search over cells and their neighbour
+ *             cells listed without repetition, then a fine search that keeps
+ *             pairs closer than a threshold; searched every n steps
+ *
+ * Readings of points the paper leaves open (each is listed in the design notes):
+ *   - the undefined force F^c in the tangential torque is the tangential force;
+ *     the torque on j is R_j n_ij x F^t_ij and the rolling torque on j is the
+ *     negative of the one on i;
+ *   - rolling torque is zero when omega_i == omega_j exactly;
+ *   - the Coulomb test and the rolling torque use the full normal force
+ *     (spring + damping); no truncation when |F^t| == 0;
+ *   - delta_t is incremented before the force is evaluated, with no projection;
+ *   - delta_t is reset to zero whenever a listed pair does not touch;
+ *   - velocity Verlet evaluates forces at x^{n+1} with v^{n+1/2};
+ *   - F = T = 0 before the first step;
+ *   - solid spheres: m = rho (4/3) pi R^3, I = (2/5) m R^2;
+ *   - search radius r_s = min(threshold, cell_factor) d_max, cell edge
+ *     h = cell_factor d_max (1 + 1e-9), skin s = r_s - d_max;
+ *   - a wall is a candidate when the centre-to-surface distance is below
+ *     R + s and above -R; walls are bodies of infinite mass and radius: R_e =
+ *     R_i, m_e = m_i, wall surface velocity at the contact point replaces the
+ *     velocity of body j, the wall's angular velocity enters the rolling term;
+ *     restitution, friction and rolling friction are the wall material's;
+ *   - unlike particle types: restitution, friction and rolling friction are the
+ *     arithmetic means of the two materials;
+ *   - particles outside the domain box become inactive at a contact search.
+ */
+#include "oracle_dem.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define PI 3.14159265358979323846
+
+typedef struct {
+  int kind; /* 0 plane, 1 cylinder */
+  double p[3];     /* plane point / axis point */
+  double nrm[3];   /* plane normal (into the domain) / axis direction */
+  int bounded;
+  double u[3], vax[3], hu, hv; /* plane extent */
+  double radius, smin, smax;   /* cylinder */
+  int inside;
+  int material;
+  double omega[3]; /* angular velocity vector of the wall */
+  double ax[3];    /* a point on the rotation axis */
+  double t_on, t_off;
+} ora_wall;
+
+typedef struct {
+  int64_t i, j; /* gid_i < gid_j */
+  double dt[3]; /* tangential overlap, orientation i -> j */
+} ora_pair;
+
+typedef struct {
+  int64_t i;
+  int32_t w;
+  double dt[3];
+} ora_wpair;
+
+struct ora_sim {
+  ora_config cfg;
+  ora_material mat[ORA_MAX_TYPES];
+  int mat_set[ORA_MAX_TYPES];
+  int64_t n;
+  double *x, *v, *w, *R, *m, *I, *F, *T, *S, *xref;
+  int32_t* type;
+  uint8_t* active;
+  double dmax, rs, rs2, h, skin;
+  int64_t nc[3];
+  int nw;
+  ora_wall walls[ORA_MAX_WALLS];
+  ora_pair* pairs;
+  int64_t npairs;
+  ora_wpair* wpairs;
+  int64_t nwpairs;
+  int64_t step;
+  int ready;
+};
+
+/* ------------------------------------------------------------------ vectors */
+
+static void vsub(const double* a, const double* b, double* r) {
+  r[0] = a[0] - b[0];
+  r[1] = a[1] - b[1];
+  r[2] = a[2] - b[2];
+}
+static double vdot(const double* a, const double* b) {
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+static void vcross(const double* a, const double* b, double* r) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double vnorm(const double* a) { return sqrt(vdot(a, a)); }
+
+/* --------------------------------------------------------------- materials */
+
+/* Table of effective parameters (Sec. 2.1). */
+static double eff_youngs(const ora_material* a, const ora_material* b) {
+  return 1.0 / ((1.0 - a->poisson * a->poisson) / a->youngs +
+                (1.0 - b->poisson * b->poisson) / b->youngs);
+}
+static double eff_shear(const ora_material* a, const ora_material* b) {
+  return 1.0 / (2.0 * (2.0 - a->poisson) * (1.0 + a->poisson) / a->youngs +
+                2.0 * (2.0 - b->poisson) * (1.0 + b->poisson) / b->youngs);
+}
+static double beta_of(double e) {
+  double le = log(e);
+  return le / sqrt(le * le + PI * PI);
+}
+
+/* Everything the Hertz-Mindlin law needs about a contact besides kinematics. */
+typedef struct {
+  double me, Re, Ye, Ge, e, mu, mur;
+} ora_contact_props;
+
+/*
+ * The nonlinear (Hertz-Mindlin) contact law, Sec. 2.1, for one contact.
+ * Inputs: overlap dn > 0, unit normal n from body i towards body j, contact
+ * relative velocity vij, relative angular velocity wrel = omega_i - omega_j,
+ * the lever arms Ri, Rj and the tangential overlap (updated in place).
+ * Outputs: the force on i (normal + tangential), the torques on i and j, and
+ * |F^n + F^t| for the force scale.
+ */
+static void hertz_mindlin(const ora_contact_props* cp, int rolling_model, double dt,
+                          double dn, const double* n, const double* vij,
+                          const double* wrel, double Ri, double Rj, double* delta_t,
+                          double* Fi, double* Mi, double* Mj, double* fmag) {
+  double vn = vdot(vij, n);
+  double vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
+  double vrt[3];
+  vsub(vij, vrn, vrt);
+  /* Eq. (delta_t): single-step accumulation, before the force is evaluated */
+  for (int k = 0; k < 3; ++k) delta_t[k] = delta_t[k] + vrt[k] * dt;
+
+  double beta = beta_of(cp->e);
+  double q = sqrt(cp->Re * dn);
+  double kn = 4.0 / 3.0 * cp->Ye * q;         /* Eq. (nonlinearkn) */
+  double kt = 8.0 * cp->Ge * q;               /* Eq. (nonlinearkt) */
+  double Sn = 2.0 * cp->Ye * q;               /* S_n */
+  double St = 8.0 * cp->Ge * q;               /* S_t */
+  double etan = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(Sn * cp->me); /* Eq. (nonlinearetan) */
+  double etat = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(St * cp->me); /* Eq. (nonlinearetat) */
+
+  double Fn[3], Ft[3];
+  for (int k = 0; k < 3; ++k) {
+    Fn[k] = -(kn * dn) * n[k] - etan * vrn[k];       /* Eq. (normal_force) */
+    Ft[k] = -(kt * delta_t[k]) - etat * vrt[k];      /* Eq. (tangential_force) */
+  }
+  double fn = vnorm(Fn);
+  double ft = vnorm(Ft);
+  /* Coulomb criterion, Eqs. (coulomb_overlap)-(coulomb_overlap3) */
+  if (ft >= cp->mu * fn && ft > 0.0) {
+    for (int k = 0; k < 3; ++k) {
+      double fhat = cp->mu * fn * Ft[k] / ft;          /* limited force */
+      double ftilde = fhat + etat * vrt[k];            /* limited elastic force */
+      delta_t[k] = ftilde / (-kt);                     /* limited overlap */
+      Ft[k] = fhat;
+    }
+  }
+  /* Eq. (torque_t) with F^c read as F^t; the torque on j acts at -R_j n */
+  double nxft[3];
+  vcross(n, Ft, nxft);
+  double Mr[3] = {0.0, 0.0, 0.0};
+  if (rolling_model == 1) {
+    /* constant rolling torque, first row of the rolling-model table */
+    double wn = vnorm(wrel);
+    if (wn > 0.0) {
+      for (int k = 0; k < 3; ++k) Mr[k] = -cp->mur * cp->Re * fn * (wrel[k] / wn);
+    }
+  }
+  double Fsum[3];
+  for (int k = 0; k < 3; ++k) {
+    Fsum[k] = Fn[k] + Ft[k];
+    Fi[k] = Fsum[k];
+    Mi[k] = Ri * nxft[k] + Mr[k];
+    Mj[k] = Rj * nxft[k] - Mr[k];
+  }
+  *fmag = vnorm(Fsum);
+}
+
+static void pp_props(const ora_sim* s, int ti, int tj, double mi, double mj, double Ri,
+                     double Rj, ora_contact_props* cp) {
+  const ora_material* a = &s->mat[ti];
+  const ora_material* b = &s->mat[tj];
+  cp->me = 1.0 / (1.0 / mi + 1.0 / mj);
+  cp->Re = 1.0 / (1.0 / Ri + 1.0 / Rj);
+  cp->Ye = eff_youngs(a, b);
+  cp->Ge = eff_shear(a, b);
+  if (ti == tj) {
+    cp->e = a->restitution;
+    cp->mu = a->friction;
+    cp->mur = a->rolling_friction;
+  } else {
+    cp->e = 0.5 * (a->restitution + b->restitution);
+    cp->mu = 0.5 * (a->friction + b->friction);
+    cp->mur = 0.5 * (a->rolling_friction + b->rolling_friction);
+  }
+}
+
+/* Particle-particle contact (i, j).  Returns 1 when the pair touches. */
+static int pp_contact(const ora_sim* s, const double* xi, const double* xj,
+                      const double* vi, const double* vj, const double* wi,
+                      const double* wj, double Ri, double Rj, double mi, double mj,
+                      int ti, int tj, double* delta_t, double* Fi, double* Mi,
+                      double* Mj, double* fmag) {
+  double dx[3];
+  vsub(xj, xi, dx);
+  double d2 = vdot(dx, dx);
+  double rsum = Ri + Rj;
+  for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = Mj[k] = 0.0;
+  *fmag = 0.0;
+  if (!(d2 < rsum * rsum)) {
+    delta_t[0] = delta_t[1] = delta_t[2] = 0.0; /* contact ended */
+    return 0;
+  }
+  double d = sqrt(d2);
+  double dn = rsum - d; /* Eq. (deltan) */
+  if (dn < 0.0) dn = 0.0;
+  double n[3] = {dx[0] / d, dx[1] / d, dx[2] / d}; /* Eq. (vecn) */
+  double rw[3] = {Ri * wi[0] + Rj * wj[0], Ri * wi[1] + Rj * wj[1],
+                  Ri * wi[2] + Rj * wj[2]};
+  double rwxn[3];
+  vcross(rw, n, rwxn);
+  double vij[3], wrel[3];
+  for (int k = 0; k < 3; ++k) {
+    vij[k] = (vi[k] - vj[k]) + rwxn[k];
+    wrel[k] = wi[k] - wj[k];
+  }
+  ora_contact_props cp;
+  pp_props(s, ti, tj, mi, mj, Ri, Rj, &cp);
+  hertz_mindlin(&cp, s->cfg.rolling_model, s->cfg.dt, dn, n, vij, wrel, Ri, Rj, delta_t,
+                Fi, Mi, Mj, fmag);
+  return 1;
+}
+
+/* ------------------------------------------------------------------- walls */
+
+/* Geometry of particle centre x against wall W.  Fills the candidate and
+   touching predicates (evaluated without square roots) and, when touching, the
+   normal from the particle to the wall, the overlap and the contact point. */
+typedef struct {
+  int candidate, touching;
+  double n[3], dn, xc[3];
+} ora_wgeo;
+
+static void wall_geometry(const ora_wall* W, const double* x, double R, double skin,
+                          ora_wgeo* g) {
+  g->candidate = g->touching = 0;
+  double rel[3];
+  vsub(x, W->p, rel);
+  if (W->kind == 0) {
+    double dist = vdot(rel, W->nrm);
+    if (W->bounded) {
+      double a = vdot(rel, W->u), b = vdot(rel, W->vax);
+      if (!(fabs(a) <= W->hu && fabs(b) <= W->hv)) return;
+    }
+    g->candidate = (dist < R + skin) && (dist > -R);
+    g->touching = dist < R;
+    if (g->touching) {
+      for (int k = 0; k < 3; ++k) {
+        g->n[k] = -W->nrm[k];
+        g->xc[k] = x[k] - dist * W->nrm[k];
+      }
+      g->dn = R - dist;
+    }
+    return;
+  }
+  /* cylinder */
+  double sax = vdot(rel, W->nrm);
+  if (!(sax >= W->smin && sax <= W->smax)) return;
+  double r[3] = {rel[0] - sax * W->nrm[0], rel[1] - sax * W->nrm[1],
+                 rel[2] - sax * W->nrm[2]};
+  double rho2 = vdot(r, r);
+  if (!(rho2 > 0.0)) return; /* centre on the axis: no defined normal */
+  double Rc = W->radius;
+  if (W->inside) {
+    /* dist = Rc - rho; candidate: -R < dist < R + s; touching: dist < R */
+    double lo = Rc - (R + skin);
+    double hi = Rc + R;
+    int above_lo = (lo <= 0.0) || (rho2 > lo * lo);
+    g->candidate = above_lo && (rho2 < hi * hi);
+    double lt = Rc - R;
+    g->touching = (lt <= 0.0) || (rho2 > lt * lt);
+  } else {
+    /* dist = rho - Rc; candidate: -R < dist < R + s; touching: dist < R */
+    double hi = Rc + R + skin;
+    double lo = Rc - R;
+    int above_lo = (lo <= 0.0) || (rho2 > lo * lo);
+    g->candidate = above_lo && (rho2 < hi * hi);
+    double lt = Rc + R;
+    g->touching = rho2 < lt * lt;
+  }
+  if (g->touching) {
+    double rho = sqrt(rho2);
+    double er[3] = {r[0] / rho, r[1] / rho, r[2] / rho};
+    double dist = W->inside ? (Rc - rho) : (rho - Rc);
+    g->dn = R - dist;
+    for (int k = 0; k < 3; ++k) {
+      g->n[k] = W->inside ? er[k] : -er[k];
+      g->xc[k] = W->p[k] + sax * W->nrm[k] + Rc * er[k];
+    }
+  }
+}
+
+static int wall_enabled(const ora_wall* W, double t) { return t >= W->t_on && t < W->t_off; }
+
+/* Particle-wall contact, same law with the wall as body j. */
+static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const double* x,
+                      const double* v, const double* w, double R, double m, int ti,
+                      double* delta_t, double* Fi, double* Mi, double* fmag) {
+  for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = 0.0;
+  *fmag = 0.0;
+  ora_wgeo g;
+  wall_geometry(W, x, R, s->skin, &g);
+  if (!wall_enabled(W, t) || !g.touching) {
+    delta_t[0] = delta_t[1] = delta_t[2] = 0.0;
+    return 0;
+  }
+  double dn = g.dn < 0.0 ? 0.0 : g.dn;
+  /* velocity of the wall surface at the contact point: Omega x (x_c - axis point) */
+  double arm[3], vw[3];
+  vsub(g.xc, W->ax, arm);
+  vcross(W->omega, arm, vw);
+  double rw[3] = {R * w[0], R * w[1], R * w[2]};
+  double rwxn[3];
+  vcross(rw, g.n, rwxn);
+  double vij[3], wrel[3];
+  for (int k = 0; k < 3; ++k) {
+    vij[k] = (v[k] - vw[k]) + rwxn[k];
+    wrel[k] = w[k] - W->omega[k];
+  }
+  const ora_material* a = &s->mat[ti];
+  const ora_material* b = &s->mat[W->material];
+  ora_contact_props cp;
+  cp.me = m;
+  cp.Re = R;
+  cp.Ye = eff_youngs(a, b);
+  cp.Ge = eff_shear(a, b);
+  cp.e = b->restitution;
+  cp.mu = b->friction;
+  cp.mur = b->rolling_friction;
+  double Mj[3];
+  hertz_mindlin(&cp, s->cfg.rolling_model, s->cfg.dt, dn, g.n, vij, wrel, R, 0.0, delta_t,
+                Fi, Mi, Mj, fmag);
+  return 1;
+}
+
+/* ------------------------------------------------------------------ search */
+
+static int cmp_pair(const void* a, const void* b) {
+  const ora_pair* p = (const ora_pair*)a;
+  const ora_pair* q = (const ora_pair*)b;
+  if (p->i != q->i) return p->i < q->i ? -1 : 1;
+  if (p->j != q->j) return p->j < q->j ? -1 : 1;
+  return 0;
+}
+
+static int64_t cell_coord(double x, double lo, double h) { return (int64_t)floor((x - lo) / h); }
+
+static int inside_domain(const ora_sim* s, const double* x) {
+  for (int k = 0; k < 3; ++k)
+    if (!(x[k] >= s->cfg.domain_lo[k] && x[k] < s->cfg.domain_hi[k])) return 0;
+  return 1;
+}
+
+/* Broad search over cells + fine search (Sec. 3.2).  Each cell is paired with
+   itself and with the 13 neighbour cells that follow it, so every pair of
+   neighbouring cells is visited once ("neighbour lists without repetition").
+   The cell lists are a list of (cell id, gid) sorted by cell, so memory stays
+   proportional to the number of particles whatever the domain size. */
+typedef struct {
+  int64_t cell, gid;
+} ora_cell_entry;
+
+static int cmp_cell_entry(const void* a, const void* b) {
+  const ora_cell_entry* p = (const ora_cell_entry*)a;
+  const ora_cell_entry* q = (const ora_cell_entry*)b;
+  if (p->cell != q->cell) return p->cell < q->cell ? -1 : 1;
+  if (p->gid != q->gid) return p->gid < q->gid ? -1 : 1;
+  return 0;
+}
+
+/* first index in E[0..m) whose cell is >= c */
+static int64_t lower_bound_cell(const ora_cell_entry* E, int64_t m, int64_t c) {
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (E[mid].cell < c)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+static int build_candidates(ora_sim* s, ora_pair** out, int64_t* nout) {
+  int64_t n = s->n;
+  ora_cell_entry* E = (ora_cell_entry*)malloc(sizeof(ora_cell_entry) * (size_t)(n > 0 ? n : 1));
+  if (!E) return ORA_ENOMEM;
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!s->active[i]) continue;
+    int64_t c[3];
+    for (int k = 0; k < 3; ++k) {
+      c[k] = cell_coord(s->x[3 * i + k], s->cfg.domain_lo[k], s->h);
+      if (c[k] < 0) c[k] = 0;
+      if (c[k] >= s->nc[k]) c[k] = s->nc[k] - 1;
+    }
+    E[m].cell = (c[2] * s->nc[1] + c[1]) * s->nc[0] + c[0];
+    E[m].gid = i;
+    ++m;
+  }
+  qsort(E, (size_t)m, sizeof(ora_cell_entry), cmp_cell_entry);
+  int64_t cap = 1024, cnt = 0;
+  ora_pair* P = (ora_pair*)malloc(sizeof(ora_pair) * (size_t)cap);
+  if (!P) {
+    free(E);
+    return ORA_ENOMEM;
+  }
+  static const int half[13][3] = {{1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},
+                                  {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1},
+                                  {0, 0, 1},  {1, 0, 1},  {-1, 1, 1}, {0, 1, 1},
+                                  {1, 1, 1}};
+  int64_t c0start = 0;
+  while (c0start < m) {
+    int64_t c0 = E[c0start].cell;
+    int64_t c0end = c0start;
+    while (c0end < m && E[c0end].cell == c0) ++c0end;
+    int64_t cx = c0 % s->nc[0], cy = (c0 / s->nc[0]) % s->nc[1], cz = c0 / (s->nc[0] * s->nc[1]);
+    for (int o = -1; o < 13; ++o) {
+      int64_t b_lo, b_hi;
+      if (o < 0) {
+        b_lo = c0start;
+        b_hi = c0end;
+      } else {
+        int64_t ox = cx + half[o][0], oy = cy + half[o][1], oz = cz + half[o][2];
+        if (ox < 0 || oy < 0 || oz < 0 || ox >= s->nc[0] || oy >= s->nc[1] || oz >= s->nc[2])
+          continue;
+        int64_t c1 = (oz * s->nc[1] + oy) * s->nc[0] + ox;
+        b_lo = lower_bound_cell(E, m, c1);
+        b_hi = lower_bound_cell(E, m, c1 + 1);
+      }
+      for (int64_t ea = c0start; ea < c0end; ++ea) {
+        int64_t a = E[ea].gid;
+        for (int64_t eb = (o < 0 ? ea + 1 : b_lo); eb < b_hi; ++eb) {
+          int64_t b = E[eb].gid;
+          double dx[3];
+          vsub(&s->x[3 * b], &s->x[3 * a], dx);
+          double d2 = vdot(dx, dx);
+          if (d2 < s->rs2) { /* fine search */
+            if (cnt == cap) {
+              cap *= 2;
+              ora_pair* Q = (ora_pair*)realloc(P, sizeof(ora_pair) * (size_t)cap);
+              if (!Q) {
+                free(P);
+                free(E);
+                return ORA_ENOMEM;
+              }
+              P = Q;
+            }
+            P[cnt].i = a < b ? a : b;
+            P[cnt].j = a < b ? b : a;
+            P[cnt].dt[0] = P[cnt].dt[1] = P[cnt].dt[2] = 0.0;
+            ++cnt;
+          }
+        }
+      }
+    }
+    c0start = c0end;
+  }
+  free(E);
+  qsort(P, (size_t)cnt, sizeof(ora_pair), cmp_pair);
+  *out = P;
+  *nout = cnt;
+  return ORA_OK;
+}
+
+/* Contact search step: deactivate escaped particles, rebuild the particle-pair
+   and particle-wall lists and carry the tangential overlap of pairs present in
+   both the old and the new list. */
+static int rebuild(ora_sim* s) {
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(s->x[3 * i + k]) || !isfinite(s->v[3 * i + k]) ||
+          !isfinite(s->w[3 * i + k]))
+        return ORA_EUNSTABLE;
+  }
+  if (s->ready) {
+    /* a contact can only be missed if a particle moved more than s/2 */
+    double lim = 0.5 * s->skin;
+    for (int64_t i = 0; i < s->n; ++i) {
+      if (!s->active[i]) continue;
+      double d[3];
+      vsub(&s->x[3 * i], &s->xref[3 * i], d);
+      if (vdot(d, d) > lim * lim) return ORA_EUNSTABLE;
+    }
+  }
+  for (int64_t i = 0; i < s->n; ++i)
+    if (s->active[i] && !inside_domain(s, &s->x[3 * i])) s->active[i] = 0;
+  memcpy(s->xref, s->x, sizeof(double) * 3 * (size_t)s->n);
+
+  ora_pair* np = NULL;
+  int64_t nn = 0;
+  int rc = build_candidates(s, &np, &nn);
+  if (rc) return rc;
+  /* merge: both lists sorted by (i, j) */
+  int64_t a = 0;
+  for (int64_t b = 0; b < nn; ++b) {
+    while (a < s->npairs && cmp_pair(&s->pairs[a], &np[b]) < 0) ++a;
+    if (a < s->npairs && cmp_pair(&s->pairs[a], &np[b]) == 0)
+      memcpy(np[b].dt, s->pairs[a].dt, sizeof(double) * 3);
+  }
+  free(s->pairs);
+  s->pairs = np;
+  s->npairs = nn;
+
+  /* particle-wall candidates, in (gid, wall id) order */
+  int64_t cap = 64, cnt = 0;
+  ora_wpair* W = (ora_wpair*)malloc(sizeof(ora_wpair) * (size_t)cap);
+  if (!W) return ORA_ENOMEM;
+  int64_t old = 0;
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int w = 0; w < s->nw; ++w) {
+      ora_wgeo g;
+      wall_geometry(&s->walls[w], &s->x[3 * i], s->R[i], s->skin, &g);
+      if (!g.candidate) continue;
+      if (cnt == cap) {
+        cap *= 2;
+        ora_wpair* Q = (ora_wpair*)realloc(W, sizeof(ora_wpair) * (size_t)cap);
+        if (!Q) {
+          free(W);
+          return ORA_ENOMEM;
+        }
+        W = Q;
+      }
+      W[cnt].i = i;
+      W[cnt].w = w;
+      W[cnt].dt[0] = W[cnt].dt[1] = W[cnt].dt[2] = 0.0;
+      while (old < s->nwpairs && (s->wpairs[old].i < i ||
+                                  (s->wpairs[old].i == i && s->wpairs[old].w < w)))
+        ++old;
+      if (old < s->nwpairs && s->wpairs[old].i == i && s->wpairs[old].w == w)
+        memcpy(W[cnt].dt, s->wpairs[old].dt, sizeof(double) * 3);
+      ++cnt;
+    }
+  }
+  free(s->wpairs);
+  s->wpairs = W;
+  s->nwpairs = cnt;
+  return ORA_OK;
+}
+
+/* ------------------------------------------------------------------ forces */
+
+static void compute_forces(ora_sim* s, double t) {
+  size_t n3 = 3 * (size_t)s->n;
+  memset(s->F, 0, sizeof(double) * n3);
+  memset(s->T, 0, sizeof(double) * n3);
+  memset(s->S, 0, sizeof(double) * (size_t)s->n);
+  for (int64_t p = 0; p < s->npairs; ++p) {
+    int64_t i = s->pairs[p].i, j = s->pairs[p].j;
+    double Fi[3], Mi[3], Mj[3], fm;
+    pp_contact(s, &s->x[3 * i], &s->x[3 * j], &s->v[3 * i], &s->v[3 * j], &s->w[3 * i],
+               &s->w[3 * j], s->R[i], s->R[j], s->m[i], s->m[j], s->type[i], s->type[j],
+               s->pairs[p].dt, Fi, Mi, Mj, &fm);
+    for (int k = 0; k < 3; ++k) {
+      s->F[3 * i + k] += Fi[k];
+      s->F[3 * j + k] -= Fi[k];
+      s->T[3 * i + k] += Mi[k];
+      s->T[3 * j + k] += Mj[k];
+    }
+    s->S[i] += fm;
+    s->S[j] += fm;
+  }
+  for (int64_t p = 0; p < s->nwpairs; ++p) {
+    int64_t i = s->wpairs[p].i;
+    double Fi[3], Mi[3], fm;
+    pw_contact(s, &s->walls[s->wpairs[p].w], t, &s->x[3 * i], &s->v[3 * i], &s->w[3 * i],
+               s->R[i], s->m[i], s->type[i], s->wpairs[p].dt, Fi, Mi, &fm);
+    for (int k = 0; k < 3; ++k) {
+      s->F[3 * i + k] += Fi[k];
+      s->T[3 * i + k] += Mi[k];
+    }
+    s->S[i] += fm;
+  }
+}
+
+/* ------------------------------------------------------------------- steps */
+
+static void kick(ora_sim* s, double h) {
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int k = 0; k < 3; ++k) {
+      double a = s->F[3 * i + k] / s->m[i] + s->cfg.gravity[k];
+      s->v[3 * i + k] = s->v[3 * i + k] + a * h;
+      s->w[3 * i + k] = s->w[3 * i + k] + (s->T[3 * i + k] / s->I[i]) * h;
+    }
+  }
+}
+
+static void drift(ora_sim* s, double dt) {
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int k = 0; k < 3; ++k) s->x[3 * i + k] = s->x[3 * i + k] + s->v[3 * i + k] * dt;
+  }
+}
+
+static int one_step(ora_sim* s) {
+  double dt = s->cfg.dt;
+  int K = s->cfg.rebuild_interval;
+  if (s->cfg.integrator == 0) {
+    /* velocity Verlet, Eqs. (halfstep)-(newvv) */
+    double h = 0.5 * dt;
+    kick(s, h);
+    drift(s, dt);
+    s->step += 1;
+    if (s->step % K == 0) {
+      int rc = rebuild(s);
+      if (rc) return rc;
+    }
+    compute_forces(s, (double)s->step * dt);
+    kick(s, h);
+  } else {
+    /* explicit Euler, Eq. (integ_EE): forces at step n, then x with v^n */
+    compute_forces(s, (double)s->step * dt);
+    for (int64_t i = 0; i < s->n; ++i) {
+      if (!s->active[i]) continue;
+      for (int k = 0; k < 3; ++k) {
+        double a = s->F[3 * i + k] / s->m[i] + s->cfg.gravity[k];
+        s->x[3 * i + k] = s->x[3 * i + k] + s->v[3 * i + k] * dt;
+        s->v[3 * i + k] = s->v[3 * i + k] + a * dt;
+        s->w[3 * i + k] = s->w[3 * i + k] + (s->T[3 * i + k] / s->I[i]) * dt;
+      }
+    }
+    s->step += 1;
+    if (s->step % K == 0) {
+      int rc = rebuild(s);
+      if (rc) return rc;
+    }
+  }
+  return ORA_OK;
+}
+
+/* --------------------------------------------------------------- interface */
+
+int ora_create(const ora_config* cfg, ora_sim** out) {
+  if (!cfg || !out) return ORA_EINVAL;
+  if (!(cfg->dt > 0.0) || cfg->rebuild_interval < 1 || cfg->integrator < 0 ||
+      cfg->integrator > 1 || cfg->rolling_model < 0 || cfg->rolling_model > 1)
+    return ORA_EINVAL;
+  if (!(cfg->neighbor_threshold >= 1.0)) return ORA_EINVAL;
+  if (!(cfg->cell_factor >= 1.0)) return ORA_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!(cfg->domain_hi[k] > cfg->domain_lo[k])) return ORA_EINVAL;
+  ora_sim* s = (ora_sim*)calloc(1, sizeof(ora_sim));
+  if (!s) return ORA_ENOMEM;
+  s->cfg = *cfg;
+  *out = s;
+  return ORA_OK;
+}
+
+static void free_particles(ora_sim* s) {
+  free(s->x); free(s->v); free(s->w); free(s->R); free(s->m); free(s->I);
+  free(s->F); free(s->T); free(s->S); free(s->xref); free(s->type); free(s->active);
+  free(s->pairs); free(s->wpairs);
+  s->x = s->v = s->w = s->R = s->m = s->I = s->F = s->T = s->S = s->xref = NULL;
+  s->type = NULL; s->active = NULL; s->pairs = NULL; s->wpairs = NULL;
+  s->npairs = s->nwpairs = 0;
+}
+
+void ora_destroy(ora_sim* s) {
+  if (!s) return;
+  free_particles(s);
+  free(s);
+}
+
+int ora_set_material(ora_sim* s, int32_t type, const ora_material* m) {
+  if (!s || !m || type < 0 || type >= ORA_MAX_TYPES) return ORA_EINVAL;
+  if (!(m->density > 0.0) || !(m->youngs > 0.0) || !(m->poisson > -1.0 && m->poisson < 0.5) ||
+      !(m->restitution > 0.0 && m->restitution <= 1.0) || !(m->friction >= 0.0) ||
+      !(m->rolling_friction >= 0.0))
+    return ORA_EINVAL;
+  s->mat[type] = *m;
+  s->mat_set[type] = 1;
+  return ORA_OK;
+}
+
+int ora_set_particles(ora_sim* s, int64_t n, const double* pos, const double* vel,
+                      const double* omega, const double* radius, const int32_t* type) {
+  if (!s || n < 0 || (n > 0 && (!pos || !radius))) return ORA_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(radius[i] > 0.0)) return ORA_EINVAL;
+    int t = type ? type[i] : 0;
+    if (t < 0 || t >= ORA_MAX_TYPES || !s->mat_set[t]) return ORA_EINVAL;
+  }
+  for (int w = 0; w < s->nw; ++w)
+    if (!s->mat_set[s->walls[w].material]) return ORA_EINVAL;
+  free_particles(s);
+  size_t n3 = 3 * (size_t)(n > 0 ? n : 1), n1 = (size_t)(n > 0 ? n : 1);
+  s->n = n;
+  s->x = (double*)calloc(n3, sizeof(double));
+  s->v = (double*)calloc(n3, sizeof(double));
+  s->w = (double*)calloc(n3, sizeof(double));
+  s->F = (double*)calloc(n3, sizeof(double));
+  s->T = (double*)calloc(n3, sizeof(double));
+  s->xref = (double*)calloc(n3, sizeof(double));
+  s->R = (double*)calloc(n1, sizeof(double));
+  s->m = (double*)calloc(n1, sizeof(double));
+  s->I = (double*)calloc(n1, sizeof(double));
+  s->S = (double*)calloc(n1, sizeof(double));
+  s->type = (int32_t*)calloc(n1, sizeof(int32_t));
+  s->active = (uint8_t*)calloc(n1, 1);
+  if (!s->x || !s->v || !s->w || !s->F || !s->T || !s->xref || !s->R || !s->m || !s->I ||
+      !s->S || !s->type || !s->active) {
+    free_particles(s);
+    return ORA_ENOMEM;
+  }
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      s->x[3 * i + k] = pos[3 * i + k];
+      s->v[3 * i + k] = vel ? vel[3 * i + k] : 0.0;
+      s->w[3 * i + k] = omega ? omega[3 * i + k] : 0.0;
+    }
+    s->R[i] = radius[i];
+    s->type[i] = type ? type[i] : 0;
+    double R = radius[i];
+    s->m[i] = s->mat[s->type[i]].density * (4.0 / 3.0) * PI * R * R * R;
+    s->I[i] = 0.4 * s->m[i] * R * R;
+    s->active[i] = 1;
+    if (R > rmax) rmax = R;
+  }
+  s->dmax = 2.0 * rmax;
+  double f = s->cfg.neighbor_threshold < s->cfg.cell_factor ? s->cfg.neighbor_threshold
+                                                            : s->cfg.cell_factor;
+  s->rs = f * s->dmax;
+  s->rs2 = s->rs * s->rs;
+  s->h = s->cfg.cell_factor * s->dmax * (1.0 + 1e-9);
+  s->skin = s->rs - s->dmax;
+  for (int k = 0; k < 3; ++k) {
+    double span = s->cfg.domain_hi[k] - s->cfg.domain_lo[k];
+    int64_t c = (int64_t)ceil(span / (s->h > 0.0 ? s->h : 1.0));
+    s->nc[k] = c < 1 ? 1 : c;
+  }
+  s->step = 0;
+  s->ready = 0;
+  int rc = rebuild(s);
+  if (rc) return rc;
+  s->ready = 1;
+  return ORA_OK;
+}
+
+static int unit3(const double* a, double* out) {
+  double nn = vnorm(a);
+  if (!(nn > 0.0) || !isfinite(nn)) return ORA_EINVAL;
+  for (int k = 0; k < 3; ++k) out[k] = a[k] / nn;
+  return ORA_OK;
+}
+
+int ora_add_plane(ora_sim* s, const double point[3], const double normal[3],
+                  const double* extent, int32_t material, const double axis_point[3],
+                  const double omega[3], double t_on, double t_off, int32_t* wall_id) {
+  if (!s || !point || !normal || s->nw >= ORA_MAX_WALLS) return ORA_EINVAL;
+  if (material < 0 || material >= ORA_MAX_TYPES || !s->mat_set[material]) return ORA_EINVAL;
+  if (s->n > 0) return ORA_ESTATE; /* walls are added before the particles */
+  ora_wall W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 0;
+  if (unit3(normal, W.nrm)) return ORA_EINVAL;
+  if (extent) {
+    double d = vdot(extent, W.nrm);
+    double u[3] = {extent[0] - d * W.nrm[0], extent[1] - d * W.nrm[1],
+                   extent[2] - d * W.nrm[2]};
+    if (unit3(u, W.u)) return ORA_EINVAL;
+    vcross(W.nrm, W.u, W.vax);
+    W.hu = extent[3];
+    W.hv = extent[4];
+    if (!(W.hu > 0.0 && W.hv > 0.0)) return ORA_EINVAL;
+    W.bounded = 1;
+  }
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = point[k];
+    W.omega[k] = omega ? omega[k] : 0.0;
+    W.ax[k] = axis_point ? axis_point[k] : point[k];
+  }
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  s->walls[s->nw] = W;
+  if (wall_id) *wall_id = s->nw;
+  s->nw += 1;
+  return ORA_OK;
+}
+
+int ora_add_cylinder(ora_sim* s, const double axis_point[3], const double axis_dir[3],
+                     double radius, double s_min, double s_max, int32_t inside,
+                     int32_t material, double omega, double t_on, double t_off,
+                     int32_t* wall_id) {
+  if (!s || !axis_point || !axis_dir || s->nw >= ORA_MAX_WALLS) return ORA_EINVAL;
+  if (material < 0 || material >= ORA_MAX_TYPES || !s->mat_set[material]) return ORA_EINVAL;
+  if (!(radius > 0.0) || !(s_max >= s_min)) return ORA_EINVAL;
+  if (s->n > 0) return ORA_ESTATE;
+  ora_wall W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 1;
+  if (unit3(axis_dir, W.nrm)) return ORA_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = axis_point[k];
+    W.ax[k] = axis_point[k];
+    W.omega[k] = omega * W.nrm[k];
+  }
+  W.radius = radius;
+  W.smin = s_min;
+  W.smax = s_max;
+  W.inside = inside ? 1 : 0;
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  s->walls[s->nw] = W;
+  if (wall_id) *wall_id = s->nw;
+  s->nw += 1;
+  return ORA_OK;
+}
+
+int ora_step(ora_sim* s, int64_t n_steps) {
+  if (!s || n_steps < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  for (int64_t k = 0; k < n_steps; ++k) {
+    int rc = one_step(s);
+    if (rc) return rc;
+  }
+  return ORA_OK;
+}
+
+int ora_get_state(ora_sim* s, double* pos, double* vel, double* omega, uint8_t* active,
+                  double* time_out) {
+  if (!s) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  size_t n3 = 3 * (size_t)s->n;
+  if (pos) memcpy(pos, s->x, sizeof(double) * n3);
+  if (vel) memcpy(vel, s->v, sizeof(double) * n3);
+  if (omega) memcpy(omega, s->w, sizeof(double) * n3);
+  if (active) memcpy(active, s->active, (size_t)s->n);
+  if (time_out) *time_out = (double)s->step * s->cfg.dt;
+  return ORA_OK;
+}
+
+int ora_get_forces(ora_sim* s, double* force, double* torque) {
+  if (!s) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  size_t n3 = 3 * (size_t)s->n;
+  if (force) memcpy(force, s->F, sizeof(double) * n3);
+  if (torque) memcpy(torque, s->T, sizeof(double) * n3);
+  return ORA_OK;
+}
+
+int ora_get_force_scale(ora_sim* s, double* scale) {
+  if (!s || !scale) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  memcpy(scale, s->S, sizeof(double) * (size_t)s->n);
+  return ORA_OK;
+}
+
+int ora_num_contacts(ora_sim* s, int64_t* n_pairs, int64_t* n_wall) {
+  if (!s) return ORA_EINVAL;
+  if (n_pairs) *n_pairs = s->npairs;
+  if (n_wall) *n_wall = s->nwpairs;
+  return ORA_OK;
+}
+
+int ora_get_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
+                     uint8_t* touching, int64_t* n_out) {
+  if (!s || cap < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  if (n_out) *n_out = s->npairs;
+  if (cap < s->npairs) return ORA_EINVAL;
+  for (int64_t p = 0; p < s->npairs; ++p) {
+    int64_t i = s->pairs[p].i, j = s->pairs[p].j;
+    if (pairs) {
+      pairs[2 * p] = i;
+      pairs[2 * p + 1] = j;
+    }
+    if (delta_t) memcpy(&delta_t[3 * p], s->pairs[p].dt, sizeof(double) * 3);
+    if (touching) {
+      double dx[3];
+      vsub(&s->x[3 * j], &s->x[3 * i], dx);
+      double rsum = s->R[i] + s->R[j];
+      touching[p] = vdot(dx, dx) < rsum * rsum;
+    }
+  }
+  return ORA_OK;
+}
+
+int ora_get_wall_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
+                          int64_t* n_out) {
+  if (!s || cap < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  if (n_out) *n_out = s->nwpairs;
+  if (cap < s->nwpairs) return ORA_EINVAL;
+  for (int64_t p = 0; p < s->nwpairs; ++p) {
+    if (pairs) {
+      pairs[2 * p] = s->wpairs[p].i;
+      pairs[2 * p + 1] = s->wpairs[p].w;
+    }
+    if (delta_t) memcpy(&delta_t[3 * p], s->wpairs[p].dt, sizeof(double) * 3);
+  }
+  return ORA_OK;
+}
+
+int ora_search_params(ora_sim* s, double* out4) {
+  if (!s || !out4) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  out4[0] = s->dmax;
+  out4[1] = s->rs;
+  out4[2] = s->h;
+  out4[3] = s->skin;
+  return ORA_OK;
+}
+
+int ora_bruteforce_candidates(ora_sim* s, int64_t cap, int64_t* pairs, int64_t* n_out) {
+  if (!s || cap < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  int64_t cnt = 0;
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int64_t j = i + 1; j < s->n; ++j) {
+      if (!s->active[j]) continue;
+      double dx[3];
+      vsub(&s->x[3 * j], &s->x[3 * i], dx);
+      if (vdot(dx, dx) < s->rs2) {
+        if (cnt < cap && pairs) {
+          pairs[2 * cnt] = i;
+          pairs[2 * cnt + 1] = j;
+        }
+        ++cnt;
+      }
+    }
+  }
+  if (n_out) *n_out = cnt;
+  return cnt > cap ? ORA_EINVAL : ORA_OK;
+}
+
+int ora_pair_force(ora_sim* s, const double xi[3], const double xj[3],
+                   const double vi[3], const double vj[3], const double wi[3],
+                   const double wj[3], double Ri, double Rj, int32_t ti, int32_t tj,
+                   double delta_t[3], double F_i[3], double M_i[3], double M_j[3],
+                   int32_t* touching) {
+  if (!s || ti < 0 || tj < 0 || ti >= ORA_MAX_TYPES || tj >= ORA_MAX_TYPES ||
+      !s->mat_set[ti] || !s->mat_set[tj] || !(Ri > 0.0) || !(Rj > 0.0))
+    return ORA_EINVAL;
+  double mi = s->mat[ti].density * (4.0 / 3.0) * PI * Ri * Ri * Ri;
+  double mj = s->mat[tj].density * (4.0 / 3.0) * PI * Rj * Rj * Rj;
+  double fm;
+  int t = pp_contact(s, xi, xj, vi, vj, wi, wj, Ri, Rj, mi, mj, ti, tj, delta_t, F_i, M_i,
+                     M_j, &fm);
+  if (touching) *touching = t;
+  return ORA_OK;
+}

@@ -1,0 +1,241 @@
+"""Seeded synthetic inputs for the DEM hot path.
+
+This module only places particles and describes walls, materials and run
+settings as plain dictionaries of numbers and numpy arrays.  It holds none of
+the method's arithmetic (no contact law, no search, no integration) and is the
+one thing that both the oracle and the GPU library consume.  Every generator is
+deterministic given its seed (numpy PCG64).
+
+Scene dictionary layout::
+
+    {"name": str,
+     "config": {dt, gravity, domain_lo, domain_hi, neighbor_threshold,
+                cell_factor, rebuild_interval, integrator, rolling_model},
+     "materials": [dict(density, youngs, poisson, restitution, friction,
+                        rolling_friction), ...],        # index = type id
+     "walls": [dict(kind="plane", point, normal, material, extent=None,
+                    axis_point=None, omega=None, t_on, t_off) |
+               dict(kind="cylinder", axis_point, axis_dir, radius, s_min, s_max,
+                    inside, material, omega, t_on, t_off), ...],
+     "particles": {pos (n,3), radius (n,), vel (n,3), omega (n,3), types (n,)}}
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+INF = float("inf")
+
+# Material of the 1,000-sphere box (d = 3 mm glass-like beads, soft modulus).
+BOX_MATERIAL = dict(density=2500.0, youngs=1.0e6, poisson=0.3, restitution=0.9,
+                    friction=0.3, rolling_friction=0.1)
+
+
+def _cfg(dt, lo, hi, threshold=1.3, cell_factor=None, K=20, integrator="verlet",
+         rolling="constant", gravity=(0.0, 0.0, -9.81)):
+    return dict(dt=float(dt), gravity=tuple(float(g) for g in gravity),
+                domain_lo=tuple(float(v) for v in lo), domain_hi=tuple(float(v) for v in hi),
+                neighbor_threshold=float(threshold),
+                cell_factor=float(threshold if cell_factor is None else cell_factor),
+                rebuild_interval=int(K), integrator=integrator, rolling_model=rolling)
+
+
+def _particles(pos, radius, vel=None, omega=None, types=None):
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = pos.shape[0]
+    radius = np.ascontiguousarray(np.broadcast_to(np.asarray(radius, dtype=np.float64), (n,)))
+    vel = np.zeros((n, 3)) if vel is None else np.ascontiguousarray(vel, dtype=np.float64).reshape(n, 3)
+    omega = np.zeros((n, 3)) if omega is None else np.ascontiguousarray(omega, dtype=np.float64).reshape(n, 3)
+    types = np.zeros(n, dtype=np.int32) if types is None else np.ascontiguousarray(types, dtype=np.int32)
+    return dict(pos=pos, radius=radius, vel=vel, omega=omega, types=types)
+
+
+def plane(point, normal, material=0, extent=None, axis_point=None, omega=None,
+          t_on=-INF, t_off=INF):
+    return dict(kind="plane", point=tuple(point), normal=tuple(normal), material=material,
+                extent=None if extent is None else tuple(extent),
+                axis_point=None if axis_point is None else tuple(axis_point),
+                omega=None if omega is None else tuple(omega), t_on=t_on, t_off=t_off)
+
+
+def cylinder(axis_point, axis_dir, radius, s_min, s_max, inside=True, material=0,
+             omega=0.0, t_on=-INF, t_off=INF):
+    return dict(kind="cylinder", axis_point=tuple(axis_point), axis_dir=tuple(axis_dir),
+                radius=float(radius), s_min=float(s_min), s_max=float(s_max),
+                inside=bool(inside), material=material, omega=float(omega), t_on=t_on,
+                t_off=t_off)
+
+
+def box_walls(lo, hi, material=0):
+    """Six planes bounding [lo, hi], normals pointing inwards."""
+    walls = []
+    for k in range(3):
+        n = [0.0, 0.0, 0.0]
+        n[k] = 1.0
+        walls.append(plane(tuple(lo), tuple(n), material))
+        n = [0.0, 0.0, 0.0]
+        n[k] = -1.0
+        walls.append(plane(tuple(hi), tuple(n), material))
+    return walls
+
+
+# --------------------------------------------------------------- placement
+
+def rsa_box(n, radius, lo, hi, rng, max_tries=200000):
+    """Random sequential addition of n equal spheres with centres in [lo, hi].
+
+    Rejection uses a hash grid of edge 2*radius; raises if it cannot place n.
+    """
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    d = 2.0 * radius
+    dims = np.maximum(1, np.ceil((hi - lo) / d).astype(np.int64))
+    grid = {}
+    pts = []
+    tries = 0
+    while len(pts) < n:
+        tries += 1
+        if tries > max_tries + 50 * n:
+            raise RuntimeError(f"rsa_box: placed only {len(pts)} of {n}")
+        p = lo + rng.random(3) * (hi - lo)
+        c = np.minimum(((p - lo) / d).astype(np.int64), dims - 1)
+        ok = True
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    for q in grid.get((c[0] + dx, c[1] + dy, c[2] + dz), ()):
+                        if np.sum((pts[q] - p) ** 2) < d * d:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            grid.setdefault((c[0], c[1], c[2]), []).append(len(pts))
+            pts.append(p)
+    return np.array(pts)
+
+
+def jittered_lattice(lo, hi, spacing, jitter, rng):
+    """Cubic lattice points in [lo, hi] with uniform jitter of +-jitter per axis."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    axes = [np.arange(lo[k], hi[k] + 1e-12, spacing) for k in range(3)]
+    g = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    g = g + rng.uniform(-jitter, jitter, size=g.shape)
+    return g
+
+
+# ------------------------------------------------------------------ scenes
+
+def box_scene(n=1000, d=3.0e-3, L=0.05, seed=0, steps_dt=1.0e-5, K=20):
+    """1,000 monodisperse spheres at seeded random non-overlapping positions in
+    a closed cube with six planar walls, gravity -z, dt = 1e-5, cell 1.2 d."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = d / 2
+    pos = rsa_box(n, R, (R, R, R), (L - R, L - R, L - R), rng)
+    lo = (-d, -d, -d)
+    hi = (L + d, L + d, L + d)
+    return dict(name=f"box_{n}", config=_cfg(steps_dt, lo, hi, threshold=1.3, cell_factor=1.2, K=K),
+                materials=[dict(BOX_MATERIAL)], walls=box_walls((0, 0, 0), (L, L, L)),
+                particles=_particles(pos, R))
+
+
+DRUM_MATERIAL = dict(density=2500.0, youngs=1.0e6, poisson=0.3, restitution=0.8,
+                     friction=0.5, rolling_friction=0.2)
+
+
+def drum_geometry_for(n, d, bulk_fill=0.35, packing=0.6, aspect=2.0):
+    """Drum radius R and length L = aspect*R holding n spheres of diameter d as
+    a bed of packing fraction `packing` that fills `bulk_fill` of the volume."""
+    vs = n * math.pi * d ** 3 / 6.0
+    vol = vs / packing / bulk_fill
+    R = (vol / (math.pi * aspect)) ** (1.0 / 3.0)
+    return R, aspect * R
+
+
+def drum_scene(n=1_000_000, d=3.0e-3, R_drum=None, L=None, omega=1.0, seed=2,
+               dt=5.0e-6, K=20, material=None, threshold=1.3, spacing=1.05, jitter=0.02):
+    """Rotating drum: n monodisperse spheres in a horizontal cylinder (axis x)
+    spinning at `omega` rad/s with two co-rotating end planes.  Particles start
+    at rest on a jittered cubic lattice (spacing 1.05 d, jitter +-0.02 d per
+    axis, so no two spheres overlap) filling the lowest part of the drum."""
+    mat = dict(DRUM_MATERIAL if material is None else material)
+    if R_drum is None or L is None:
+        R_drum, L = drum_geometry_for(n, d)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = d / 2
+    a = spacing * d
+    # generate lattice points in the box hull with a margin, keep those inside
+    lo = (-L / 2 + r * 1.2, -R_drum + r * 1.2, -R_drum + r * 1.2)
+    hi = (L / 2 - r * 1.2, R_drum - r * 1.2, R_drum - r * 1.2)
+    # only the lower part is needed: estimate the height to keep memory small
+    g = jittered_lattice(lo, hi, a, jitter * d, rng)
+    rho = np.sqrt(g[:, 1] ** 2 + g[:, 2] ** 2)
+    keep = (rho < R_drum - 1.2 * r) & (np.abs(g[:, 0]) < L / 2 - 1.2 * r)
+    g = g[keep]
+    if g.shape[0] < n:
+        raise RuntimeError(f"drum too small: {g.shape[0]} lattice sites < {n}")
+    order = np.lexsort((g[:, 0], g[:, 1], g[:, 2]))  # lowest z first
+    g = g[order[:n]]
+    # shuffle so that the input order carries no spatial structure
+    g = g[rng.permutation(n)]
+    m = 2 * d
+    dlo = (-L / 2 - m, -R_drum - m, -R_drum - m)
+    dhi = (L / 2 + m, R_drum + m, R_drum + m)
+    walls = [
+        cylinder((0.0, 0.0, 0.0), (1.0, 0.0, 0.0), R_drum, -L / 2, L / 2, True, 0, omega),
+        plane((-L / 2, 0.0, 0.0), (1.0, 0.0, 0.0), 0, None, (0.0, 0.0, 0.0), (omega, 0.0, 0.0)),
+        plane((L / 2, 0.0, 0.0), (-1.0, 0.0, 0.0), 0, None, (0.0, 0.0, 0.0), (omega, 0.0, 0.0)),
+    ]
+    return dict(name=f"drum_{n}", config=_cfg(dt, dlo, dhi, threshold=threshold, K=K),
+                materials=[mat], walls=walls, particles=_particles(g, r),
+                geometry=dict(R=R_drum, L=L, omega=omega))
+
+
+def dense_snapshot(n=3000, d=3.0e-3, seed=7, overlap=0.01, vmax=0.05, wmax=20.0,
+                   polydisperse=0.0, n_types=1, dt=1.0e-5, K=5, walls=True,
+                   rolling="constant", integrator="verlet", friction=None,
+                   threshold=1.3):
+    """A jammed-like random snapshot that exercises every branch of the law:
+    jittered lattice with spacing slightly below d (so many pairs overlap),
+    random translational and angular velocities, optional size spread and
+    several materials, inside a box of six walls some of which touch spheres."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = int(math.ceil(n ** (1 / 3)))
+    a = d * (1.0 - overlap)
+    pts = np.stack(np.meshgrid(*[np.arange(side) * a] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pts = pts[:n] + rng.uniform(-0.003 * d, 0.003 * d, size=(n, 3))
+    radius = np.full(n, d / 2)
+    if polydisperse > 0:
+        radius = radius * (1.0 - polydisperse * rng.random(n))
+    pts = pts - pts.min(axis=0) + d
+    vel = rng.uniform(-vmax, vmax, size=(n, 3))
+    om = rng.uniform(-wmax, wmax, size=(n, 3))
+    types = rng.integers(0, n_types, size=n).astype(np.int32)
+    mats = []
+    for t in range(n_types):
+        m = dict(BOX_MATERIAL)
+        m["restitution"] = [0.9, 0.5, 0.7, 0.3][t % 4]
+        m["friction"] = [0.3, 0.1, 0.5, 0.05][t % 4] if friction is None else friction
+        m["youngs"] = [1.0e6, 5.0e6, 2.0e6, 1.0e7][t % 4]
+        m["poisson"] = [0.3, 0.25, 0.35, 0.2][t % 4]
+        m["density"] = [2500.0, 3000.0, 2000.0, 7850.0][t % 4]
+        mats.append(m)
+    hi_box = pts.max(axis=0) + d
+    wl = []
+    if walls:
+        # walls placed so that the outermost spheres slightly overlap them
+        lo_w = pts.min(axis=0) - 0.45 * d
+        hi_w = pts.max(axis=0) + 0.45 * d
+        wl = box_walls(tuple(lo_w), tuple(hi_w), material=0)
+    lo = (0.0, 0.0, 0.0)
+    hi = tuple(hi_box + d)
+    return dict(name=f"dense_{n}", config=_cfg(dt, lo, hi, threshold=threshold, K=K,
+                                                 rolling=rolling, integrator=integrator),
+                materials=mats, walls=wl,
+                particles=_particles(pts, radius, vel, om, types))
