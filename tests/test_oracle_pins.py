@@ -628,3 +628,87 @@ def test_invalid_arguments(oracle_built):
     with pytest.raises(OracleError):
         s.set_material(0, density=-1, youngs=1, poisson=0.3, restitution=0.5, friction=0.1,
                        rolling_friction=0.0)
+
+
+def test_friction_opposes_contact_point_slip_particle_pair(oracle_built):
+    """A spinning sphere pressed on a static one: the contact point of i moves
+    with omega_i x (R_i n); the tangential force on i opposes that motion and
+    its torque opposes the spin (relative velocity of Sec. 2.1)."""
+    s = sim_with(mat=dict(MAT, rolling_friction=0.0, friction=0.5))
+    R = 1.5e-3
+    rng = np.random.default_rng(8)
+    z = np.zeros(3)
+    for _ in range(20):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        w = rng.normal(0, 30, 3)
+        out = s.pair_force(z, (2 * R - 1e-5) * n, z, z, w, z, R, R)
+        slip = np.cross(w, R * n)
+        Ft = out["F"] - np.dot(out["F"], n) * n
+        assert np.dot(Ft, slip) < -0.99 * np.linalg.norm(Ft) * np.linalg.norm(slip)
+        assert np.dot(out["Mi"], w - np.dot(w, n) * n) < 0
+
+
+def test_coulomb_truncation_keeps_force_continuous(oracle_built):
+    """Eqs. (coulomb_overlap)-(coulomb_overlap3): the truncated overlap is the
+    limited force *plus* the damping part, so that re-evaluating at a lower
+    sliding speed drops below the limit (sticks) instead of staying pinned at
+    it; without the damping part the force would jump."""
+    mat = dict(MAT, friction=0.2, restitution=0.3)
+    dt = 1e-5
+    s = sim_with(mat=mat, dt=dt)
+    R = 1.5e-3
+    n = np.array([0.0, 0.0, 1.0])
+    xi, xj = np.zeros(3), (2 * R - 1e-5) * n
+    z = np.zeros(3)
+    v = np.array([1e-3, 0.0, 0.0])  # slow sliding: damping below the limit
+    a = s.pair_force(xi, xj, v, z, z, z, R, R, delta_t=(2e-5, 0, 0))
+    Fa = a["F"] - np.dot(a["F"], n) * n
+    fn = abs(np.dot(a["F"], n))
+    assert np.linalg.norm(Fa) == pytest.approx(0.2 * fn, rel=1e-12)
+    # re-evaluate at half the sliding speed, cancelling the history increment
+    b = s.pair_force(xi, xj, v / 2, z, z, z, R, R, delta_t=a["delta_t"] - v / 2 * dt)
+    Fb = b["F"] - np.dot(b["F"], n) * n
+    assert np.linalg.norm(Fb) < 0.2 * fn * (1 - 1e-3)
+    assert Fb[0] < 0  # still opposes the sliding
+
+
+def test_tangential_oscillation_of_resting_sphere(oracle_built):
+    """A sphere resting on a plane, kicked tangentially with mu large: the
+    contact-point displacement u obeys the linear oscillator
+    (2m/7) u'' = -k_t u - eta_t u' (translation and rotation both respond), with
+    Mindlin's k_t = 8 G_e sqrt(R delta_eq).  The measured frequency pins k_t, the
+    lever arm and the moment of inertia; the measured decay rate pins eta_t."""
+    e = 0.9
+    mat = dict(MAT, friction=5.0, rolling_friction=0.0, restitution=e)
+    R = 1.5e-3
+    dt = 1e-6
+    s = sim_with(mat=mat, dt=dt, K=10**9)
+    s.add_plane((0, 0, 0), (0, 0, 1))
+    m = mat["density"] * 4 / 3 * math.pi * R ** 3
+    Ye = eff(mat, mat)
+    Ge = 1.0 / (2 * 2 * (2 - 0.3) * (1 + 0.3) / mat["youngs"])
+    deq = (3 * m * 9.81 / (4 * Ye * math.sqrt(R))) ** (2 / 3)
+    s.set_particles([[0, 0, R - deq]], [R], vel=[[1e-4, 0, 0]])
+    ts, us = [], []
+    for k in range(12000):
+        s.step(1)
+        st = s.state()
+        us.append(st["vel"][0, 0] - R * st["omega"][0, 1])
+        ts.append((k + 1) * dt)
+    us = np.array(us)
+    ts = np.array(ts)
+    kt = 8 * Ge * math.sqrt(R * deq)
+    w0 = math.sqrt(7 * kt / (2 * m))
+    beta = math.log(e) / math.sqrt(math.log(e) ** 2 + math.pi ** 2)
+    zeta_expect = 7 * (-2 * math.sqrt(5 / 6) * beta * math.sqrt(kt * m)) / (4 * m * w0)
+    # zero crossings of u' give the damped period, peaks the decay
+    sgn = np.sign(us)
+    cross = np.where(np.diff(sgn) != 0)[0]
+    tc = ts[cross] - us[cross] * (ts[cross + 1] - ts[cross]) / (us[cross + 1] - us[cross])
+    period = 2 * np.mean(np.diff(tc[:6]))
+    wd = 2 * math.pi / period
+    assert wd == pytest.approx(w0 * math.sqrt(1 - zeta_expect ** 2), rel=5e-3)
+    peaks = [np.max(np.abs(us[cross[i]:cross[i + 1] + 1])) for i in range(5)]
+    decay = np.log(peaks[0] / peaks[4]) / (4 * period / 2)
+    assert decay == pytest.approx(zeta_expect * w0, rel=3e-2)
