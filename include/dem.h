@@ -1,0 +1,210 @@
+/*
+ * dem.h - C ABI of the MI355X (gfx950) soft-sphere DEM library (libdem.so).
+ *
+ * The library runs the data-parallel hot path of the soft-sphere discrete
+ * element method of Golshan et al., "Lethe-DEM: an open-source parallel
+ * discrete element solver with load balancing" (arXiv 2106.09576):
+ *   - contact search every K steps ("constant" detection, Sec. 3.1): particles
+ *     sorted into a uniform cell grid, broad search over neighbouring cells,
+ *     fine search keeping pairs closer than r_s = threshold * d_max;
+ *   - nonlinear Hertz-Mindlin particle-particle and particle-wall contact
+ *     forces with tangential-overlap history, Coulomb limit with overlap
+ *     truncation and constant-torque rolling resistance (Sec. 2.1);
+ *   - velocity Verlet or explicit Euler integration of translation and
+ *     rotation (Sec. 2.2).
+ *
+ * Conventions for every function:
+ *   - returns 0 (DEM_OK) on success or a negative DEM_E* code; dem_last_error()
+ *     gives a message for the calling thread;
+ *   - host arrays passed in are copied before the call returns; output host
+ *     arrays are caller-owned and filled in particle-input order ("gid" =
+ *     index in the array given to dem_set_particles);
+ *   - "*_device" variants take device pointers (e.g. PyTorch tensors'
+ *     data_ptr()) that stay owned by the caller; they are read or written on
+ *     the library's stream, which waits for the configured hip_stream first;
+ *   - vectors are 3 doubles (x, y, z), arrays of vectors are n x 3 row-major;
+ *   - a context is not thread-safe; separate contexts are independent;
+ *   - call order: dem_create -> dem_set_material -> dem_add_*_wall ->
+ *     dem_set_particles -> dem_step / dem_get_*.  Calling dem_set_particles
+ *     again restarts the simulation (time 0, all contact history cleared).
+ */
+#ifndef DEM_H
+#define DEM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dem_ctx dem_ctx; /* opaque context */
+
+enum {
+  DEM_OK = 0,
+  DEM_EINVAL = -1,     /* invalid argument (message says which)               */
+  DEM_EHIP = -2,       /* a HIP runtime call failed                           */
+  DEM_ENOMEM = -3,     /* device or host allocation failed                    */
+  DEM_ECAPACITY = -4,  /* more neighbours or wall contacts than the capacity  */
+  DEM_EUNSTABLE = -5,  /* non-finite state, or a particle moved more than half
+                          the search skin between two searches (a contact may
+                          have been missed); the state stops at that search  */
+  DEM_ESTATE = -6,     /* call order violated, or a previous error is sticky  */
+  DEM_ENODEV = -7      /* no usable gfx950 device                              */
+};
+
+/* Material of a particle type or of a wall (physical-properties section of the
+   paper's parameter file): density [kg/m^3], Young's modulus Y [Pa], Poisson
+   ratio nu, restitution coefficient e in (0, 1], Coulomb friction mu >= 0,
+   rolling friction mu_r >= 0. */
+typedef struct {
+  double density, youngs, poisson, restitution, friction, rolling_friction;
+} dem_material;
+
+typedef struct {
+  double dt;                 /* time step [s] */
+  double gravity[3];         /* [m/s^2] */
+  double domain_lo[3];       /* domain box: the cell grid covers [lo, hi); a   */
+  double domain_hi[3];       /* particle outside becomes inactive at a search  */
+  double neighbor_threshold; /* r_s / d_max (paper default 1.3, Sec. 3.2) */
+  double cell_factor;        /* cell edge h / d_max; r_s = min(threshold,
+                                cell_factor) * d_max, so h >= r_s always */
+  int32_t rebuild_interval;  /* K: contact search every K steps (Sec. 3.1) */
+  int32_t integrator;        /* 0 velocity Verlet (Eqs. halfstep/newvv),
+                                1 explicit Euler (Eq. integ_EE) */
+  int32_t rolling_model;     /* 0 none, 1 constant torque (Sec. 2.1 table) */
+  int32_t precision;         /* 0 plain FP64; 1 contact law in FP32 with
+                                positions, velocities, tangential history and
+                                force sums in FP64 */
+  int32_t n_instances;       /* must be 1 */
+  int32_t max_neighbors;     /* candidate neighbours kept per particle;
+                                0 = derived from r_s and the smallest radius */
+  void* hip_stream;          /* optional hipStream_t the library orders its
+                                work after (and that waits for the library);
+                                NULL = none */
+} dem_config;
+
+typedef struct {
+  int64_t n_particles;     /* particles given to dem_set_particles          */
+  int64_t n_active;        /* not deactivated by leaving the domain box     */
+  int64_t n_list_entries;  /* directed candidate entries (2 per pair)       */
+  int64_t n_touching;      /* directed entries whose spheres overlap        */
+  int64_t n_wall_candidates;
+  int64_t step;            /* steps completed since dem_set_particles       */
+  int64_t n_rebuilds;      /* contact searches run, including the first     */
+  int32_t max_neighbors;   /* capacity per particle in use                  */
+  int32_t precision;
+  double r_s, cell_size, skin, d_max;
+  int64_t n_cells;         /* cells of the grid (padded to 4x4x4 bricks)    */
+  int64_t device_bytes;    /* device memory held by the context             */
+} dem_stats;
+
+/* Create a context on the current HIP device.  cfg is copied.  Fails with
+   DEM_EINVAL for dt <= 0, an empty domain, rebuild_interval < 1, threshold or
+   cell_factor < 1, an unknown integrator/rolling model/precision or
+   n_instances != 1; DEM_ENODEV if the device is not gfx950. */
+int dem_create(const dem_config* cfg, dem_ctx** out_ctx);
+/* Release every device buffer of the context.  NULL is ignored. */
+void dem_destroy(dem_ctx* ctx);
+/* Message of the last error on the calling thread ("" if none). */
+const char* dem_last_error(dem_ctx* ctx);
+
+/* Material of particle type / wall material id `type` (0 <= type < 16).
+   instance must be 0. */
+int dem_set_material(dem_ctx* ctx, int32_t instance, int32_t type, const dem_material* m);
+
+/* Planar wall through `point` with unit `normal` pointing into the domain
+   (normalised here; a zero vector is DEM_EINVAL).  extent: NULL = infinite,
+   else 5 doubles {u_x, u_y, u_z, half_u, half_v}: u is projected into the
+   plane, v = normal x u, and the wall acts only where the particle centre
+   projects inside the rectangle (no edge contacts).  The wall's surface
+   moves with velocity omega x (x_c - axis_point) at the contact point x_c
+   (NULL omega = static; NULL axis_point = point); the geometry itself does
+   not move, so omega should be parallel to the normal.  The wall acts for
+   t_on <= t < t_off (floating walls, Sec. 3.7).  Writes its id to *wall_id
+   (may be NULL).  Walls are added before dem_set_particles (else
+   DEM_ESTATE); at most 32 walls. */
+int dem_add_planar_wall(dem_ctx* ctx, int32_t instance, const double point[3],
+                        const double normal[3], const double* extent, int32_t material,
+                        const double axis_point[3], const double omega[3], double t_on,
+                        double t_off, int32_t* wall_id);
+
+/* Cylindrical wall of radius `radius` around the axis through axis_point
+   along axis_dir (normalised), acting where the axial coordinate
+   s = (x - axis_point).axis_dir lies in [s_min, s_max]; inside != 0 keeps
+   particles inside the cylinder, 0 outside.  The wall spins at `omega` rad/s
+   about the axis (surface velocity omega axis_dir x (x_c - axis_point)).
+   Same activity window and ordering rules as the planar wall. */
+int dem_add_cylinder_wall(dem_ctx* ctx, int32_t instance, const double axis_point[3],
+                          const double axis_dir[3], double radius, double s_min, double s_max,
+                          int32_t inside, int32_t material, double omega, double t_on,
+                          double t_off, int32_t* wall_id);
+
+/* Set n >= 0 particles (instance 0): positions (n x 3), velocities and
+   angular velocities (n x 3, NULL = zero), radii (n, > 0) and material types
+   (n, NULL = type 0; each type's material must be set).  Masses are
+   rho (4/3) pi R^3 and moments of inertia (2/5) m R^2.  Allocates the
+   device state, runs the first contact search at these positions with all
+   tangential overlaps zero, and sets the stored forces to zero (the first
+   velocity-Verlet half kick sees gravity only).  DEM_ECAPACITY if a particle
+   already has more neighbours than max_neighbors. */
+int dem_set_particles(dem_ctx* ctx, int32_t instance, int64_t n, const double* pos,
+                      const double* vel, const double* omega, const double* radius,
+                      const int32_t* type);
+/* Same with device pointers (caller-owned, read on the library's stream). */
+int dem_set_particles_device(dem_ctx* ctx, int32_t instance, int64_t n, const double* pos,
+                             const double* vel, const double* omega, const double* radius,
+                             const int32_t* type);
+
+/* Advance n_steps >= 0 steps.  Synchronous: returns after the work finished.
+   Contact searches run at every step number that is a multiple of
+   rebuild_interval.  Errors (DEM_EUNSTABLE, DEM_ECAPACITY) are sticky: the
+   state is frozen at the step where they were detected and later dem_step
+   calls return DEM_ESTATE until dem_set_particles is called again. */
+int dem_step(dem_ctx* ctx, int64_t n_steps);
+
+/* Current state in input order: positions, velocities, angular velocities
+   (n x 3 each), active flags (n) and time; any pointer may be NULL. */
+int dem_get_state(dem_ctx* ctx, int32_t instance, double* pos, double* vel, double* omega,
+                  uint8_t* active, double* time_out);
+/* Same into device buffers (caller-owned; written on the library's stream,
+   complete when the call returns). */
+int dem_get_state_device(dem_ctx* ctx, int32_t instance, double* pos, double* vel,
+                         double* omega, uint8_t* active);
+
+/* Total contact force and torque on every particle from the last force
+   evaluation of the last dem_step call (zero before the first step). */
+int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque);
+
+/* Candidate particle pairs of the current contact list, each once as
+   (gid_i, gid_j) with gid_i < gid_j, sorted; delta_t = tangential overlap of
+   the pair oriented from i to j (3 per pair); touching = 1 if the spheres
+   overlap at the current positions.  *n_out receives the count; if it
+   exceeds cap nothing else is written and DEM_EINVAL is returned. */
+int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
+                     double* delta_t, uint8_t* touching, int64_t* n_out);
+/* Particle-wall candidates as (gid, wall_id), sorted, with their tangential
+   overlaps.  Same capacity rule. */
+int dem_get_wall_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
+                          double* delta_t, int64_t* n_out);
+
+/* Re-sort particles into cells and rebuild the contact lists at the current
+   positions without moving them (the tangential overlaps are carried over);
+   for testing the history carry-over and for restarts. */
+int dem_resort(dem_ctx* ctx);
+
+/* Counters of the current state (runs a small reduction on the device). */
+int dem_get_stats(dem_ctx* ctx, dem_stats* out);
+
+/* Stream the library launches on (hipStream_t), for timing with events. */
+void* dem_stream(dem_ctx* ctx);
+
+/* Benchmark instrumentation.  While enabled, dem_step launches every kernel
+   directly (no graphs) and records HIP events around each force launch and
+   each contact search; dem_get_timing writes {force ms total, force launches,
+   search ms total, searches} accumulated since dem_set_timing was called. */
+int dem_set_timing(dem_ctx* ctx, int32_t enable);
+int dem_get_timing(dem_ctx* ctx, double* out4);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEM_H */

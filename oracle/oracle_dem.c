@@ -25,7 +25,8 @@
  *             velocity Verlet
  *   Sec. 3.2                       broad search over cells and their neighbour
  *             cells listed without repetition, then a fine search that keeps
- *             pairs closer than a threshold; searched every n steps
+ *             pairs closer than a threshold; Sec. 3.1: searched every n steps
+ *   Sec. 3.7                       moving (rotating) and floating walls
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
  *   - the undefined force F^c in the tangential torque is the tangential force;

@@ -1,0 +1,1067 @@
+// Host runtime of the MI355X DEM library: the C ABI declared in include/dem.h.
+//
+// A context owns all device buffers of one simulation, one HIP stream (default
+// priority) and up to four instantiated HIP graphs, one per parity of the
+// ping-pong buffers, each holding one K-step chunk: the contact search
+// (Sec. 3.2, every K steps as in the "constant" detection of Sec. 3.1) followed
+// by K force+integration launches and a clock tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dem.h"
+#include "dem_device.hpp"
+
+using namespace demgpu;
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr double kPi = 3.14159265358979323846;
+
+int set_err(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+}  // namespace
+
+struct dem_ctx {
+  dem_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_user = nullptr;
+  dem_material mat[kMaxTypes]{};
+  bool mat_set[kMaxTypes]{};
+  std::vector<WallDev> walls;
+
+  // particle state
+  int n = 0;
+  bool ready = false;
+  bool failed = false;
+  int fail_code = 0;
+  int max_nb = 0;
+  int64_t cap = 0;
+  GridDev grid{};
+  StepParams sp{};
+  double dmax = 0, rs = 0, h = 0, skin = 0;
+
+  std::vector<void*> allocs;
+  size_t dev_bytes = 0;
+  double4 *pos[2]{}, *vel[2]{}, *omg[2]{};
+  int *gid[2]{}, *info[2]{};
+  double4 *F[2]{}, *T[2]{};
+  double4* xref = nullptr;
+  int* wid[2]{};
+  double* whist[2]{};
+  int* nbr[2]{};
+  double* hist[2]{};
+  int* rowlen[2]{};
+  uint32_t* keys = nullptr;
+  int *rank = nullptr, *count = nullptr, *start = nullptr, *tile_sums = nullptr;
+  int *perm0 = nullptr, *perm = nullptr;
+  PairCoef *d_pp = nullptr, *d_pw = nullptr;
+  WallDev* d_walls = nullptr;
+  int* d_flags = nullptr;
+  int64_t* d_clock = nullptr;
+  unsigned long long* d_stats = nullptr;
+
+  int cur = 0;   // parity of pos/vel/omg (flips at every force launch and reorder)
+  int pcur = 0;  // parity of gid/info/F/T/wall slots/neighbour list (flips at reorder)
+  int64_t step = 0;
+  int64_t host_base = 0;  // value of the device clock
+  int64_t n_rebuilds = 0;
+  hipGraphExec_t graph[2][2]{};
+
+  // optional per-kernel timing (benchmarks): events around force launches
+  bool timing = false;
+  std::vector<hipEvent_t> tev;
+  std::vector<int> tkind;  // 0 force, 1 search chunk
+  double t_force_ms = 0, t_search_ms = 0;
+  int64_t n_force = 0, n_search = 0;
+};
+
+namespace {
+
+#define HIPCHK(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return set_err(DEM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+  } while (0)
+
+int dalloc(dem_ctx* c, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return set_err(DEM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  c->allocs.push_back(*p);
+  c->dev_bytes += bytes;
+  return DEM_OK;
+}
+
+template <typename T>
+int dalloc_t(dem_ctx* c, T** p, size_t count) {
+  return dalloc(c, (void**)p, count * sizeof(T));
+}
+
+void destroy_graphs(dem_ctx* c) {
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      if (c->graph[a][b]) {
+        (void)hipGraphExecDestroy(c->graph[a][b]);
+        c->graph[a][b] = nullptr;
+      }
+}
+
+void free_particles(dem_ctx* c) {
+  destroy_graphs(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  c->dev_bytes = 0;
+  c->ready = false;
+  c->n = 0;
+}
+
+int check_instance(int32_t instance) {
+  if (instance != 0) return set_err(DEM_EINVAL, "instance %d: only instance 0 exists", instance);
+  return DEM_OK;
+}
+
+int wait_user(dem_ctx* c) {
+  if (c->cfg.hip_stream) {
+    HIPCHK(hipEventRecord(c->ev_user, (hipStream_t)c->cfg.hip_stream));
+    HIPCHK(hipStreamWaitEvent(c->stream, c->ev_user, 0));
+  }
+  return DEM_OK;
+}
+
+int finish(dem_ctx* c) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DEM_OK;
+}
+
+bool unit3(const double* a, double* out) {
+  double nn = sqrt((a[0] * a[0] + a[1] * a[1]) + a[2] * a[2]);
+  if (!(nn > 0.0) || !std::isfinite(nn)) return false;
+  for (int k = 0; k < 3; ++k) out[k] = a[k] / nn;
+  return true;
+}
+
+// Effective parameters (Sec. 2.1 table) per material pair.
+double eff_youngs(const dem_material& a, const dem_material& b) {
+  return 1.0 / ((1.0 - a.poisson * a.poisson) / a.youngs +
+                (1.0 - b.poisson * b.poisson) / b.youngs);
+}
+double eff_shear(const dem_material& a, const dem_material& b) {
+  return 1.0 / (2.0 * (2.0 - a.poisson) * (1.0 + a.poisson) / a.youngs +
+                2.0 * (2.0 - b.poisson) * (1.0 + b.poisson) / b.youngs);
+}
+double damping_factor(double e) {
+  double le = log(e);
+  double beta = le / sqrt(le * le + kPi * kPi);
+  return -2.0 * sqrt(5.0 / 6.0) * beta;
+}
+
+// ------------------------------------------------------------ kernel groups
+
+ParticleBufs pbufs(dem_ctx* c, int k) { return ParticleBufs{c->pos[k], c->vel[k], c->omg[k]}; }
+NbrList nlist(dem_ctx* c, int k) { return NbrList{c->nbr[k], c->hist[k], c->rowlen[k], c->cap}; }
+WallSlots wslots(dem_ctx* c, int k) { return WallSlots{c->wid[k], c->whist[k]}; }
+
+// Contact search: counting sort into cells, reorder, particle-wall search and
+// particle-pair search with history carry-over.  Flips both parities.
+int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
+  hipStream_t s = c->stream;
+  const int a = c->cur, p = c->pcur;
+  HIPCHK(launch_fill_i32(c->count, 0, c->grid.n_keys + 1, s));
+  HIPCHK(launch_keys(c->grid, c->sp, c->pos[a], c->vel[a], c->info[p], c->xref, check_guard,
+                     c->keys, c->rank, c->count, c->d_flags, s));
+  HIPCHK(launch_scan(c->count, c->start, c->grid.n_keys + 1, c->tile_sums, s));
+  HIPCHK(launch_scatter(c->n, c->keys, c->rank, c->start, c->perm0, s));
+  HIPCHK(launch_cell_rank(c->n, c->grid.n_keys, c->perm0, c->keys, c->start, c->gid[p],
+                          c->perm, s));
+  HIPCHK(launch_reorder(c->sp, c->perm, pbufs(c, a), pbufs(c, a ^ 1), c->gid[p], c->gid[p ^ 1],
+                        c->info[p], c->info[p ^ 1], c->xref, wslots(c, p), wslots(c, p ^ 1),
+                        c->d_walls, move_forces ? c->F[p] : nullptr,
+                        move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
+                        c->d_flags, s));
+  HIPCHK(launch_search(c->grid, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
+                       nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
+  c->cur ^= 1;
+  c->pcur ^= 1;
+  c->n_rebuilds += 1;
+  return DEM_OK;
+}
+
+int enqueue_force(dem_ctx* c, int mode, int64_t step_rel) {
+  const int a = c->cur, p = c->pcur;
+  HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_pp, c->d_pw, c->d_walls, pbufs(c, a),
+                      pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
+                      c->d_clock, step_rel, c->d_flags, c->stream));
+  c->cur ^= 1;
+  return DEM_OK;
+}
+
+int timed_begin(dem_ctx* c, int kind) {
+  if (!c->timing) return DEM_OK;
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventRecord(e, c->stream));
+  c->tev.push_back(e);
+  c->tkind.push_back(kind);
+  return DEM_OK;
+}
+
+int timed_end(dem_ctx* c) {
+  if (!c->timing) return DEM_OK;
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventRecord(e, c->stream));
+  c->tev.push_back(e);
+  c->tkind.push_back(-1);
+  return DEM_OK;
+}
+
+int collect_timing(dem_ctx* c) {
+  if (!c->timing) return DEM_OK;
+  for (size_t k = 0; k + 1 < c->tev.size(); k += 2) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->tev[k], c->tev[k + 1]));
+    if (c->tkind[k] == 0) {
+      c->t_force_ms += ms;
+      c->n_force += 1;
+    } else {
+      c->t_search_ms += ms;
+      c->n_search += 1;
+    }
+  }
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  c->tev.clear();
+  c->tkind.clear();
+  return DEM_OK;
+}
+
+int eager_rebuild(dem_ctx* c) {
+  int rc = timed_begin(c, 1);
+  if (rc) return rc;
+  rc = enqueue_rebuild(c, 1, 0);
+  if (rc) return rc;
+  return timed_end(c);
+}
+
+int eager_force(dem_ctx* c, int mode, int64_t step_rel) {
+  int rc = timed_begin(c, 0);
+  if (rc) return rc;
+  rc = enqueue_force(c, mode, step_rel);
+  if (rc) return rc;
+  return timed_end(c);
+}
+
+int set_clock(dem_ctx* c, int64_t value) {
+  if (c->host_base != value) {
+    HIPCHK(launch_tick(c->d_clock, value - c->host_base, c->stream));
+    c->host_base = value;
+  }
+  return DEM_OK;
+}
+
+// One K-step chunk captured in a graph, for the current parities.
+int get_chunk_graph(dem_ctx* c, hipGraphExec_t* out) {
+  hipGraphExec_t& g = c->graph[c->cur][c->pcur];
+  if (g) {
+    *out = g;
+    return DEM_OK;
+  }
+  const int K = c->cfg.rebuild_interval;
+  const int save_cur = c->cur, save_pcur = c->pcur;
+  const int64_t save_rb = c->n_rebuilds;
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = DEM_OK;
+  if (c->cfg.integrator == 0) {
+    rc = enqueue_rebuild(c, 1, 0);
+    for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 0, j);
+  } else {
+    for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 2, j);
+    if (rc == DEM_OK) rc = enqueue_rebuild(c, 1, 0);
+  }
+  if (rc == DEM_OK) {
+    hipError_t e = launch_tick(c->d_clock, K, c->stream);
+    if (e != hipSuccess) rc = set_err(DEM_EHIP, "tick launch: %s", hipGetErrorString(e));
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->cur = save_cur;
+  c->pcur = save_pcur;
+  c->n_rebuilds = save_rb;
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return set_err(DEM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g = nullptr;
+    return set_err(DEM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return DEM_OK;
+}
+
+int launch_chunk(dem_ctx* c, int64_t clock_at_start) {
+  int rc = set_clock(c, clock_at_start);
+  if (rc) return rc;
+  hipGraphExec_t g = nullptr;
+  rc = get_chunk_graph(c, &g);
+  if (rc) return rc;
+  HIPCHK(hipGraphLaunch(g, c->stream));
+  const int K = c->cfg.rebuild_interval;
+  c->cur ^= (K + 1) & 1;
+  c->pcur ^= 1;
+  c->n_rebuilds += 1;
+  c->host_base += K;
+  return DEM_OK;
+}
+
+int read_flags(dem_ctx* c, int* flags) {
+  HIPCHK(hipMemcpyAsync(flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DEM_OK;
+}
+
+int flags_to_error(dem_ctx* c, int flags) {
+  if (flags == 0) return DEM_OK;
+  c->failed = true;
+  if (flags & (kFlagNbrOverflow | kFlagWallOverflow)) {
+    c->fail_code = DEM_ECAPACITY;
+    return set_err(DEM_ECAPACITY,
+                   "capacity exceeded (flags 0x%x): more than %d neighbours or %d wall "
+                   "contacts for a particle; raise max_neighbors",
+                   flags, c->max_nb, kWallSlots);
+  }
+  c->fail_code = DEM_EUNSTABLE;
+  if (flags & kFlagNonFinite)
+    return set_err(DEM_EUNSTABLE, "non-finite particle state (flags 0x%x)", flags);
+  return set_err(DEM_EUNSTABLE,
+                 "a particle moved more than half the skin (%.3g m) between two contact "
+                 "searches; lower rebuild_interval or dt (flags 0x%x)",
+                 c->skin, flags);
+}
+
+// host copy of the current particle arrays in sorted order
+struct HostSnapshot {
+  std::vector<double4> pos, vel, omg;
+  std::vector<int> gid, info;
+};
+
+int snapshot(dem_ctx* c, HostSnapshot& h, bool want_pos, bool want_vel, bool want_omg) {
+  const size_t n = (size_t)c->n;
+  h.gid.resize(n);
+  h.info.resize(n);
+  HIPCHK(hipMemcpyAsync(h.gid.data(), c->gid[c->pcur], n * sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipMemcpyAsync(h.info.data(), c->info[c->pcur], n * sizeof(int),
+                        hipMemcpyDeviceToHost, c->stream));
+  if (want_pos) {
+    h.pos.resize(n);
+    HIPCHK(hipMemcpyAsync(h.pos.data(), c->pos[c->cur], n * sizeof(double4),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (want_vel) {
+    h.vel.resize(n);
+    HIPCHK(hipMemcpyAsync(h.vel.data(), c->vel[c->cur], n * sizeof(double4),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (want_omg) {
+    h.omg.resize(n);
+    HIPCHK(hipMemcpyAsync(h.omg.data(), c->omg[c->cur], n * sizeof(double4),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return DEM_OK;
+}
+
+int require_ready(dem_ctx* c) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  if (!c->ready) return set_err(DEM_ESTATE, "particles not set (call dem_set_particles)");
+  return DEM_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char* dem_last_error(dem_ctx*) { return g_err.c_str(); }
+
+void* dem_stream(dem_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int dem_create(const dem_config* cfg, dem_ctx** out) {
+  if (!cfg || !out) return set_err(DEM_EINVAL, "null argument");
+  *out = nullptr;
+  if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return set_err(DEM_EINVAL, "dt must be > 0");
+  for (int k = 0; k < 3; ++k)
+    if (!(cfg->domain_hi[k] > cfg->domain_lo[k]))
+      return set_err(DEM_EINVAL, "empty domain along axis %d", k);
+  if (cfg->rebuild_interval < 1) return set_err(DEM_EINVAL, "rebuild_interval must be >= 1");
+  if (!(cfg->neighbor_threshold >= 1.0))
+    return set_err(DEM_EINVAL, "neighbor_threshold must be >= 1");
+  if (!(cfg->cell_factor >= 1.0)) return set_err(DEM_EINVAL, "cell_factor must be >= 1");
+  if (cfg->integrator < 0 || cfg->integrator > 1)
+    return set_err(DEM_EINVAL, "integrator must be 0 (Verlet) or 1 (Euler)");
+  if (cfg->rolling_model < 0 || cfg->rolling_model > 1)
+    return set_err(DEM_EINVAL, "rolling_model must be 0 or 1");
+  if (cfg->precision < 0 || cfg->precision > 1)
+    return set_err(DEM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 law)");
+  if (cfg->n_instances != 1) return set_err(DEM_EINVAL, "n_instances must be 1");
+  if (cfg->max_neighbors < 0 || cfg->max_neighbors > 4096)
+    return set_err(DEM_EINVAL, "max_neighbors out of range");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return set_err(DEM_ENODEV, "no HIP device: %s", hipGetErrorString(e));
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, dev);
+  if (e != hipSuccess) return set_err(DEM_ENODEV, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_err(DEM_ENODEV, "device %d is %s, this library is built for gfx950", dev,
+                   prop.gcnArchName);
+  dem_ctx* c = new dem_ctx();
+  c->cfg = *cfg;
+  c->device = dev;
+  e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    return set_err(DEM_EHIP, "stream/event creation: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return DEM_OK;
+}
+
+void dem_destroy(dem_ctx* c) {
+  if (!c) return;
+  free_particles(c);
+  for (hipEvent_t ev : c->tev) (void)hipEventDestroy(ev);
+  if (c->ev_user) (void)hipEventDestroy(c->ev_user);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int dem_set_material(dem_ctx* c, int32_t instance, int32_t type, const dem_material* m) {
+  if (!c || !m) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(instance)) return rc;
+  if (type < 0 || type >= kMaxTypes) return set_err(DEM_EINVAL, "type %d out of [0, 16)", type);
+  if (!(m->density > 0.0) || !(m->youngs > 0.0) || !(m->poisson > -1.0 && m->poisson < 0.5) ||
+      !(m->restitution > 0.0 && m->restitution <= 1.0) || !(m->friction >= 0.0) ||
+      !(m->rolling_friction >= 0.0))
+    return set_err(DEM_EINVAL, "invalid material values for type %d", type);
+  if (c->ready) return set_err(DEM_ESTATE, "materials are set before dem_set_particles");
+  c->mat[type] = *m;
+  c->mat_set[type] = true;
+  return DEM_OK;
+}
+
+int dem_add_planar_wall(dem_ctx* c, int32_t instance, const double point[3],
+                        const double normal[3], const double* extent, int32_t material,
+                        const double axis_point[3], const double omega[3], double t_on,
+                        double t_off, int32_t* wall_id) {
+  if (!c || !point || !normal) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(instance)) return rc;
+  if ((int)c->walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !c->mat_set[material])
+    return set_err(DEM_EINVAL, "wall material %d not set", material);
+  if (c->ready) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  WallDev W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 0;
+  if (!unit3(normal, W.nrm)) return set_err(DEM_EINVAL, "zero or non-finite wall normal");
+  if (extent) {
+    double d = (extent[0] * W.nrm[0] + extent[1] * W.nrm[1]) + extent[2] * W.nrm[2];
+    double u[3] = {extent[0] - d * W.nrm[0], extent[1] - d * W.nrm[1], extent[2] - d * W.nrm[2]};
+    if (!unit3(u, W.u)) return set_err(DEM_EINVAL, "extent axis parallel to the normal");
+    W.vax[0] = W.nrm[1] * W.u[2] - W.nrm[2] * W.u[1];
+    W.vax[1] = W.nrm[2] * W.u[0] - W.nrm[0] * W.u[2];
+    W.vax[2] = W.nrm[0] * W.u[1] - W.nrm[1] * W.u[0];
+    W.hu = extent[3];
+    W.hv = extent[4];
+    if (!(W.hu > 0.0 && W.hv > 0.0)) return set_err(DEM_EINVAL, "extent half-widths must be > 0");
+    W.bounded = 1;
+  }
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = point[k];
+    W.omega[k] = omega ? omega[k] : 0.0;
+    W.ax[k] = axis_point ? axis_point[k] : point[k];
+  }
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  if (wall_id) *wall_id = (int32_t)c->walls.size();
+  c->walls.push_back(W);
+  return DEM_OK;
+}
+
+int dem_add_cylinder_wall(dem_ctx* c, int32_t instance, const double axis_point[3],
+                          const double axis_dir[3], double radius, double s_min, double s_max,
+                          int32_t inside, int32_t material, double omega, double t_on,
+                          double t_off, int32_t* wall_id) {
+  if (!c || !axis_point || !axis_dir) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(instance)) return rc;
+  if ((int)c->walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !c->mat_set[material])
+    return set_err(DEM_EINVAL, "wall material %d not set", material);
+  if (!(radius > 0.0) || !(s_max >= s_min))
+    return set_err(DEM_EINVAL, "cylinder needs radius > 0 and s_max >= s_min");
+  if (c->ready) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  WallDev W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 1;
+  if (!unit3(axis_dir, W.nrm)) return set_err(DEM_EINVAL, "zero or non-finite axis");
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = axis_point[k];
+    W.ax[k] = axis_point[k];
+    W.omega[k] = omega * W.nrm[k];
+  }
+  W.radius = radius;
+  W.smin = s_min;
+  W.smax = s_max;
+  W.inside = inside ? 1 : 0;
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  if (wall_id) *wall_id = (int32_t)c->walls.size();
+  c->walls.push_back(W);
+  return DEM_OK;
+}
+
+int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos,
+                      const double* vel, const double* omega, const double* radius,
+                      const int32_t* type) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  if (int rc = check_instance(instance)) return rc;
+  if (n < 0 || n > (int64_t)1 << 30) return set_err(DEM_EINVAL, "n out of range");
+  if (n > 0 && (!pos || !radius)) return set_err(DEM_EINVAL, "pos and radius are required");
+  double rmin = INFINITY, rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!(radius[i] > 0.0) || !std::isfinite(radius[i]))
+      return set_err(DEM_EINVAL, "radius[%lld] must be > 0", (long long)i);
+    int t = type ? type[i] : 0;
+    if (t < 0 || t >= kMaxTypes || !c->mat_set[t])
+      return set_err(DEM_EINVAL, "particle %lld has type %d without material", (long long)i, t);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(pos[3 * i + k]) || (vel && !std::isfinite(vel[3 * i + k])) ||
+          (omega && !std::isfinite(omega[3 * i + k])))
+        return set_err(DEM_EINVAL, "non-finite state of particle %lld", (long long)i);
+    rmin = std::min(rmin, radius[i]);
+    rmax = std::max(rmax, radius[i]);
+  }
+  free_particles(c);
+  c->failed = false;
+  c->fail_code = 0;
+  c->n = (int)n;
+
+  // search geometry: r_s = min(threshold, cell_factor) d_max, h >= r_s
+  c->dmax = 2.0 * rmax;
+  const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
+  c->rs = f * c->dmax;
+  c->h = c->cfg.cell_factor * c->dmax * (1.0 + 1e-9);
+  c->skin = c->rs - c->dmax;
+  GridDev& g = c->grid;
+  int64_t nkeys = 64;
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = c->cfg.domain_lo[k];
+    g.hi[k] = c->cfg.domain_hi[k];
+    double span = g.hi[k] - g.lo[k];
+    double cc = n > 0 ? ceil(span / c->h) : 1.0;
+    if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
+    g.nc[k] = std::max(1, (int)cc);
+    g.nb[k] = (g.nc[k] + 3) / 4;
+    nkeys *= g.nb[k];
+  }
+  if (nkeys > ((int64_t)1 << 30))
+    return set_err(DEM_EINVAL, "cell grid of %lld cells is too large; shrink the domain box",
+                   (long long)nkeys);
+  g.h = n > 0 ? c->h : 1.0;
+  g.n_keys = nkeys;
+
+  // neighbour capacity: spheres of radius rmin whose centres lie within r_s of
+  // a centre fit in a ball of radius r_s + rmin (packing density <= 0.7405),
+  // with 25% margin for overlaps
+  int max_nb = c->cfg.max_neighbors;
+  if (max_nb == 0) {
+    double ratio = n > 0 ? (c->rs + rmin) / rmin : 2.0;
+    double bound = 0.7405 * ratio * ratio * ratio * 1.25;
+    max_nb = (int)std::min(512.0, std::max(16.0, ceil(bound)));
+  }
+  c->max_nb = max_nb;
+  const int64_t npad = ((n + 63) / 64) * 64;
+  c->cap = npad * max_nb;
+
+  StepParams& sp = c->sp;
+  sp.dt = c->cfg.dt;
+  sp.hdt = 0.5 * c->cfg.dt;
+  for (int k = 0; k < 3; ++k) sp.g[k] = c->cfg.gravity[k];
+  sp.rs2 = c->rs * c->rs;
+  sp.guard2 = (0.5 * c->skin) * (0.5 * c->skin);
+  sp.skin = c->skin;
+  sp.n = (int)n;
+  sp.max_nb = max_nb;
+  sp.n_walls = (int)c->walls.size();
+  sp.rolling = c->cfg.rolling_model;
+
+  // allocations
+  const size_t N = (size_t)std::max<int64_t>(n, 1);
+  int rc = DEM_OK;
+  for (int b = 0; b < 2 && rc == DEM_OK; ++b) {
+    rc = rc ? rc : dalloc_t(c, &c->pos[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->vel[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->omg[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->gid[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->info[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->F[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->T[b], N);
+    rc = rc ? rc : dalloc_t(c, &c->wid[b], N * kWallSlots);
+    rc = rc ? rc : dalloc_t(c, &c->whist[b], N * kWallSlots * 3);
+    rc = rc ? rc : dalloc_t(c, &c->nbr[b], (size_t)std::max<int64_t>(c->cap, 1));
+    rc = rc ? rc : dalloc_t(c, &c->hist[b], (size_t)std::max<int64_t>(c->cap, 1) * 3);
+    rc = rc ? rc : dalloc_t(c, &c->rowlen[b], N);
+  }
+  rc = rc ? rc : dalloc_t(c, &c->xref, N);
+  rc = rc ? rc : dalloc_t(c, &c->keys, N);
+  rc = rc ? rc : dalloc_t(c, &c->rank, N);
+  rc = rc ? rc : dalloc_t(c, &c->count, (size_t)nkeys + 1);
+  rc = rc ? rc : dalloc_t(c, &c->start, (size_t)nkeys + 2);
+  rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((nkeys + 1 + 1023) / 1024 + 1));
+  rc = rc ? rc : dalloc_t(c, &c->perm0, N);
+  rc = rc ? rc : dalloc_t(c, &c->perm, N);
+  rc = rc ? rc : dalloc_t(c, &c->d_pp, (size_t)kMaxTypes * kMaxTypes);
+  rc = rc ? rc : dalloc_t(c, &c->d_pw, (size_t)kMaxTypes * kMaxTypes);
+  rc = rc ? rc : dalloc_t(c, &c->d_walls, (size_t)kMaxWalls);
+  rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
+  rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
+  rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
+  if (rc) {
+    free_particles(c);
+    return rc;
+  }
+
+  // material-pair tables
+  std::vector<PairCoef> pp(kMaxTypes * kMaxTypes), pw(kMaxTypes * kMaxTypes);
+  memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
+  memset(pw.data(), 0, pw.size() * sizeof(PairCoef));
+  for (int a = 0; a < kMaxTypes; ++a)
+    for (int b = 0; b < kMaxTypes; ++b) {
+      if (!c->mat_set[a] || !c->mat_set[b]) continue;
+      const dem_material &A = c->mat[a], &B = c->mat[b];
+      PairCoef& q = pp[a * kMaxTypes + b];
+      q.Ye = eff_youngs(A, B);
+      q.Ge = eff_shear(A, B);
+      double e = a == b ? A.restitution : 0.5 * (A.restitution + B.restitution);
+      q.ceta = damping_factor(e);
+      q.mu = a == b ? A.friction : 0.5 * (A.friction + B.friction);
+      q.mur = a == b ? A.rolling_friction : 0.5 * (A.rolling_friction + B.rolling_friction);
+      PairCoef& r = pw[a * kMaxTypes + b];  // particle type a against wall material b
+      r.Ye = q.Ye;
+      r.Ge = q.Ge;
+      r.ceta = damping_factor(B.restitution);
+      r.mu = B.friction;
+      r.mur = B.rolling_friction;
+    }
+
+  // packed particle state
+  std::vector<double4> hpos(N), hvel(N), homg(N);
+  std::vector<int> hgid(N), hinfo(N);
+  for (int64_t i = 0; i < n; ++i) {
+    const int t = type ? type[i] : 0;
+    const double R = radius[i];
+    const double m = c->mat[t].density * (4.0 / 3.0) * kPi * R * R * R;
+    const double I = 0.4 * m * R * R;
+    hpos[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], R);
+    hvel[i] = vel ? make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], m)
+                  : make_double4(0.0, 0.0, 0.0, m);
+    homg[i] = omega ? make_double4(omega[3 * i], omega[3 * i + 1], omega[3 * i + 2], I)
+                    : make_double4(0.0, 0.0, 0.0, I);
+    hgid[i] = (int)i;
+    hinfo[i] = t;
+  }
+  hipStream_t s = c->stream;
+  if ((rc = wait_user(c))) return rc;
+  HIPCHK(hipMemcpyAsync(c->d_pp, pp.data(), pp.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_pw, pw.data(), pw.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
+  if (!c->walls.empty())
+    HIPCHK(hipMemcpyAsync(c->d_walls, c->walls.data(), c->walls.size() * sizeof(WallDev),
+                          hipMemcpyHostToDevice, s));
+  c->cur = 0;
+  c->pcur = 0;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(c->pos[0], hpos.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->vel[0], hvel.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->omg[0], homg.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->gid[0], hgid.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->info[0], hinfo.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  // zero-filled: forces of both parities, empty old list and wall slots
+  HIPCHK(launch_fill_i32((int*)c->F[0], 0, (int64_t)N * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->T[0], 0, (int64_t)N * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->F[1], 0, (int64_t)N * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->T[1], 0, (int64_t)N * 8, s));
+  HIPCHK(launch_fill_i32(c->rowlen[0], 0, (int64_t)N, s));
+  HIPCHK(launch_fill_i32(c->wid[0], -1, (int64_t)N * kWallSlots, s));
+  HIPCHK(launch_fill_i32(c->d_flags, 0, 1, s));
+  HIPCHK(launch_fill_i32((int*)c->d_clock, 0, 2, s));
+  HIPCHK(launch_fill_i32((int*)c->xref, 0, (int64_t)N * 8, s));
+  c->step = 0;
+  c->host_base = 0;
+  c->n_rebuilds = 0;
+  if ((rc = enqueue_rebuild(c, 0, 0))) return rc;
+  int flags = 0;
+  if ((rc = read_flags(c, &flags))) return rc;
+  c->ready = true;
+  return flags_to_error(c, flags);
+}
+
+int dem_set_particles_device(dem_ctx* c, int32_t instance, int64_t n, const double* pos,
+                             const double* vel, const double* omega, const double* radius,
+                             const int32_t* type) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  if (n < 0 || n > (int64_t)1 << 30) return set_err(DEM_EINVAL, "n out of range");
+  // validation needs the values on the host; stage them once
+  std::vector<double> hp(3 * (size_t)n), hv, hw, hr((size_t)n);
+  std::vector<int32_t> ht;
+  if (int rc = wait_user(c)) return rc;
+  if (n > 0) {
+    if (!pos || !radius) return set_err(DEM_EINVAL, "pos and radius are required");
+    HIPCHK(hipMemcpyAsync(hp.data(), pos, hp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hr.data(), radius, hr.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    if (vel) {
+      hv.resize(3 * (size_t)n);
+      HIPCHK(hipMemcpyAsync(hv.data(), vel, hv.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (omega) {
+      hw.resize(3 * (size_t)n);
+      HIPCHK(hipMemcpyAsync(hw.data(), omega, hw.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    }
+    if (type) {
+      ht.resize((size_t)n);
+      HIPCHK(hipMemcpyAsync(ht.data(), type, ht.size() * 4, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return dem_set_particles(c, instance, n, hp.data(), vel ? hv.data() : nullptr,
+                           omega ? hw.data() : nullptr, hr.data(), type ? ht.data() : nullptr);
+}
+
+int dem_step(dem_ctx* c, int64_t n_steps) {
+  if (int rc = require_ready(c)) return rc;
+  if (n_steps < 0) return set_err(DEM_EINVAL, "n_steps must be >= 0");
+  if (c->failed)
+    return set_err(DEM_ESTATE, "a previous error (%d) is sticky; call dem_set_particles",
+                   c->fail_code);
+  if (n_steps == 0 || c->n == 0) {
+    c->step += n_steps;
+    return DEM_OK;
+  }
+  int rc = wait_user(c);
+  if (rc) return rc;
+  const int64_t K = c->cfg.rebuild_interval;
+  const int64_t s0 = c->step, s_end = s0 + n_steps;
+  const bool graphs = !c->timing;
+  if (c->cfg.integrator == 0) {
+    HIPCHK(launch_kick_drift(c->sp, pbufs(c, c->cur), c->info[c->pcur], c->F[c->pcur],
+                             c->T[c->pcur], c->stream));
+    int64_t s = s0 + 1;
+    while (s <= s_end) {
+      if (graphs && s % K == 0 && s + K - 1 <= s_end - 1) {
+        if ((rc = launch_chunk(c, s))) return rc;
+        s += K;
+        continue;
+      }
+      if (s % K == 0 && (rc = eager_rebuild(c))) return rc;
+      if ((rc = eager_force(c, s < s_end ? 0 : 1, s - c->host_base))) return rc;
+      s += 1;
+    }
+  } else {
+    int64_t s = s0 + 1;
+    while (s <= s_end) {
+      if (graphs && (s - 1) % K == 0 && s + K - 1 <= s_end) {
+        if ((rc = launch_chunk(c, s - 1))) return rc;
+        s += K;
+        continue;
+      }
+      if ((rc = eager_force(c, 2, (s - 1) - c->host_base))) return rc;
+      if (s % K == 0 && (rc = eager_rebuild(c))) return rc;
+      s += 1;
+    }
+  }
+  c->step = s_end;
+  int flags = 0;
+  if ((rc = read_flags(c, &flags))) return rc;
+  if ((rc = collect_timing(c))) return rc;
+  return flags_to_error(c, flags);
+}
+
+int dem_get_state(dem_ctx* c, int32_t instance, double* pos, double* vel, double* omega,
+                  uint8_t* active, double* time_out) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(instance)) return rc;
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, pos != nullptr, vel != nullptr, omega != nullptr)) return rc;
+  for (int p = 0; p < c->n; ++p) {
+    const int g = h.gid[p];
+    if (pos) {
+      pos[3 * g] = h.pos[p].x;
+      pos[3 * g + 1] = h.pos[p].y;
+      pos[3 * g + 2] = h.pos[p].z;
+    }
+    if (vel) {
+      vel[3 * g] = h.vel[p].x;
+      vel[3 * g + 1] = h.vel[p].y;
+      vel[3 * g + 2] = h.vel[p].z;
+    }
+    if (omega) {
+      omega[3 * g] = h.omg[p].x;
+      omega[3 * g + 1] = h.omg[p].y;
+      omega[3 * g + 2] = h.omg[p].z;
+    }
+    if (active) active[g] = (h.info[p] & kInactive) ? 0 : 1;
+  }
+  if (time_out) *time_out = (double)c->step * c->cfg.dt;
+  return DEM_OK;
+}
+
+int dem_get_state_device(dem_ctx* c, int32_t instance, double* pos, double* vel, double* omega,
+                         uint8_t* active) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(instance)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<double> p(pos ? 3 * n : 0), v(vel ? 3 * n : 0), w(omega ? 3 * n : 0);
+  std::vector<uint8_t> a(active ? n : 0);
+  int rc = dem_get_state(c, instance, pos ? p.data() : nullptr, vel ? v.data() : nullptr,
+                         omega ? w.data() : nullptr, active ? a.data() : nullptr, nullptr);
+  if (rc) return rc;
+  if (pos) HIPCHK(hipMemcpyAsync(pos, p.data(), p.size() * 8, hipMemcpyHostToDevice, c->stream));
+  if (vel) HIPCHK(hipMemcpyAsync(vel, v.data(), v.size() * 8, hipMemcpyHostToDevice, c->stream));
+  if (omega) HIPCHK(hipMemcpyAsync(omega, w.data(), w.size() * 8, hipMemcpyHostToDevice, c->stream));
+  if (active) HIPCHK(hipMemcpyAsync(active, a.data(), a.size(), hipMemcpyHostToDevice, c->stream));
+  return finish(c);
+}
+
+int dem_get_forces(dem_ctx* c, int32_t instance, double* force, double* torque) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(instance)) return rc;
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<double4> F(n), T(n);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(F.data(), c->F[c->pcur], n * sizeof(double4), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(T.data(), c->T[c->pcur], n * sizeof(double4), hipMemcpyDeviceToHost,
+                          c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  for (size_t p = 0; p < n; ++p) {
+    const int g = h.gid[p];
+    if (force) {
+      force[3 * g] = F[p].x;
+      force[3 * g + 1] = F[p].y;
+      force[3 * g + 2] = F[p].z;
+    }
+    if (torque) {
+      torque[3 * g] = T[p].x;
+      torque[3 * g + 1] = T[p].y;
+      torque[3 * g + 2] = T[p].z;
+    }
+  }
+  return DEM_OK;
+}
+
+int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, double* delta_t,
+                     uint8_t* touching, int64_t* n_out) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(instance)) return rc;
+  if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, true, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> rl(n), nb((size_t)c->cap);
+  std::vector<double> hs((size_t)c->cap * 3);
+  const int L = c->pcur;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(rl.data(), c->rowlen[L], n * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(nb.data(), c->nbr[L], (size_t)c->cap * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hs.data(), c->hist[L], (size_t)c->cap * 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  struct Rec {
+    int64_t i, j;
+    double d[3];
+    uint8_t t;
+  };
+  std::vector<Rec> out;
+  for (size_t p = 0; p < n; ++p) {
+    for (int k = 0; k < rl[p]; ++k) {
+      const int64_t e = nbr_entry((int)p, k, c->max_nb);
+      const int q = nb[(size_t)e];
+      if (h.gid[p] >= h.gid[q]) continue;
+      Rec r;
+      r.i = h.gid[p];
+      r.j = h.gid[q];
+      r.d[0] = hs[(size_t)e];
+      r.d[1] = hs[(size_t)c->cap + (size_t)e];
+      r.d[2] = hs[2 * (size_t)c->cap + (size_t)e];
+      const double dx = h.pos[q].x - h.pos[p].x, dy = h.pos[q].y - h.pos[p].y,
+                   dz = h.pos[q].z - h.pos[p].z;
+      const double rsum = h.pos[p].w + h.pos[q].w;
+      r.t = ((dx * dx + dy * dy) + dz * dz) < rsum * rsum ? 1 : 0;
+      out.push_back(r);
+    }
+  }
+  std::sort(out.begin(), out.end(),
+            [](const Rec& a, const Rec& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+  if (n_out) *n_out = (int64_t)out.size();
+  if ((int64_t)out.size() > cap) return set_err(DEM_EINVAL, "cap %lld < %zu contacts", (long long)cap, out.size());
+  for (size_t m = 0; m < out.size(); ++m) {
+    if (pairs) {
+      pairs[2 * m] = out[m].i;
+      pairs[2 * m + 1] = out[m].j;
+    }
+    if (delta_t)
+      for (int k = 0; k < 3; ++k) delta_t[3 * m + k] = out[m].d[k];
+    if (touching) touching[m] = out[m].t;
+  }
+  return DEM_OK;
+}
+
+int dem_get_wall_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
+                          double* delta_t, int64_t* n_out) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(instance)) return rc;
+  if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> w(n * kWallSlots);
+  std::vector<double> wh(n * kWallSlots * 3);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(w.data(), c->wid[c->pcur], w.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(wh.data(), c->whist[c->pcur], wh.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  struct Rec {
+    int64_t i, w;
+    double d[3];
+  };
+  std::vector<Rec> out;
+  for (size_t p = 0; p < n; ++p)
+    for (int s = 0; s < kWallSlots; ++s) {
+      const int wi = w[(size_t)s * n + p];
+      if (wi < 0) break;
+      Rec r;
+      r.i = h.gid[p];
+      r.w = wi;
+      for (int k = 0; k < 3; ++k) r.d[k] = wh[(size_t)(3 * s + k) * n + p];
+      out.push_back(r);
+    }
+  std::sort(out.begin(), out.end(),
+            [](const Rec& a, const Rec& b) { return a.i != b.i ? a.i < b.i : a.w < b.w; });
+  if (n_out) *n_out = (int64_t)out.size();
+  if ((int64_t)out.size() > cap) return set_err(DEM_EINVAL, "cap %lld < %zu wall contacts", (long long)cap, out.size());
+  for (size_t m = 0; m < out.size(); ++m) {
+    if (pairs) {
+      pairs[2 * m] = out[m].i;
+      pairs[2 * m + 1] = out[m].w;
+    }
+    if (delta_t)
+      for (int k = 0; k < 3; ++k) delta_t[3 * m + k] = out[m].d[k];
+  }
+  return DEM_OK;
+}
+
+int dem_resort(dem_ctx* c) {
+  if (int rc = require_ready(c)) return rc;
+  if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
+  if (int rc = wait_user(c)) return rc;
+  if (c->n == 0) return DEM_OK;
+  if (int rc = enqueue_rebuild(c, 0, 1)) return rc;
+  int flags = 0;
+  if (int rc = read_flags(c, &flags)) return rc;
+  return flags_to_error(c, flags);
+}
+
+int dem_get_stats(dem_ctx* c, dem_stats* out) {
+  if (int rc = require_ready(c)) return rc;
+  if (!out) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = wait_user(c)) return rc;
+  unsigned long long v[4] = {0, 0, 0, 0};
+  if (c->n > 0) {
+    HIPCHK(launch_fill_i32((int*)c->d_stats, 0, 8, c->stream));
+    HIPCHK(launch_stats(c->sp, c->pos[c->cur], c->info[c->pcur], nlist(c, c->pcur),
+                        wslots(c, c->pcur), c->d_stats, c->stream));
+    HIPCHK(hipMemcpyAsync(v, c->d_stats, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  memset(out, 0, sizeof(*out));
+  out->n_particles = c->n;
+  out->n_active = (int64_t)v[0];
+  out->n_list_entries = (int64_t)v[1];
+  out->n_touching = (int64_t)v[2];
+  out->n_wall_candidates = (int64_t)v[3];
+  out->step = c->step;
+  out->n_rebuilds = c->n_rebuilds;
+  out->max_neighbors = c->max_nb;
+  out->precision = c->cfg.precision;
+  out->r_s = c->rs;
+  out->cell_size = c->h;
+  out->skin = c->skin;
+  out->d_max = c->dmax;
+  out->n_cells = c->grid.n_keys;
+  out->device_bytes = (int64_t)c->dev_bytes;
+  return DEM_OK;
+}
+
+// Per-kernel timing for benchmarks: when enabled, dem_step launches eagerly
+// (no graphs) with HIP events around every force launch and every contact
+// search; dem_get_timing returns the accumulated milliseconds and counts.
+int dem_set_timing(dem_ctx* c, int32_t enable) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  c->timing = enable != 0;
+  c->t_force_ms = c->t_search_ms = 0;
+  c->n_force = c->n_search = 0;
+  return DEM_OK;
+}
+
+int dem_get_timing(dem_ctx* c, double* out4) {
+  if (!c || !out4) return set_err(DEM_EINVAL, "null argument");
+  out4[0] = c->t_force_ms;
+  out4[1] = (double)c->n_force;
+  out4[2] = c->t_search_ms;
+  out4[3] = (double)c->n_search;
+  return DEM_OK;
+}
+
+}  // extern "C"

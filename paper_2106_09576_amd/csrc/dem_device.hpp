@@ -1,0 +1,136 @@
+// Device-side data structures and kernel launch interface of the MI355X DEM
+// library.  Shared by the HIP kernels (dem_kernels.hip) and the host runtime
+// behind the C ABI (dem_api.hip).  Nothing here is visible to library users.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace demgpu {
+
+constexpr int kMaxTypes = 16;
+constexpr int kMaxWalls = 32;
+constexpr int kWallSlots = 4;   // particle-wall contacts kept per particle
+constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+constexpr int kTypeMask = 0xffff;
+constexpr int kInactive = 1 << 16;  // flag bit in the per-particle info word
+
+// Sticky error bits raised by kernels (read once per dem_step call).
+enum : int {
+  kFlagGuard = 1,         // a particle moved more than skin/2 between searches
+  kFlagNonFinite = 2,     // NaN/Inf in the state
+  kFlagNbrOverflow = 4,   // a particle had more candidate neighbours than max_nb
+  kFlagWallOverflow = 8,  // more wall candidates than kWallSlots
+};
+
+// Per material pair constants of the Hertz-Mindlin law (effective-parameter
+// table of Sec. 2.1): effective Young's and shear moduli, the damping factor
+// -2 sqrt(5/6) beta, friction and rolling friction of the pair.
+struct PairCoef {
+  double Ye, Ge, ceta, mu, mur, pad0, pad1, pad2;
+};
+
+// Analytic wall.  kind 0: plane (point p, unit normal nrm into the domain,
+// optional rectangular extent along u / vax).  kind 1: cylinder (axis point p,
+// unit axis nrm, radius, axial range [smin, smax], particles inside or
+// outside).  Rotation: surface velocity omega x (x_c - ax).  Active for
+// t_on <= t < t_off.
+struct WallDev {
+  int kind, bounded, inside, material;
+  double p[3], nrm[3], u[3], vax[3];
+  double hu, hv, radius, smin, smax;
+  double omega[3], ax[3];
+  double t_on, t_off;
+};
+
+// Uniform cell grid: cell (cx,cy,cz) = floor((x - lo)/h); cells are ordered
+// in 4x4x4 bricks (Morton order inside a brick), one extra key for inactive
+// particles at the end.
+struct GridDev {
+  double lo[3], hi[3], h;
+  int nc[3];
+  int nb[3];
+  int64_t n_keys;  // 64 * nb0 * nb1 * nb2
+};
+
+struct StepParams {
+  double dt, hdt;
+  double g[3];
+  double rs2;      // squared search radius
+  double guard2;   // (skin/2)^2
+  double skin;
+  int n;           // number of particles (active + inactive)
+  int max_nb;      // neighbour slots per particle
+  int n_walls;
+  int rolling;     // 0 none, 1 constant torque
+};
+
+// Particle arrays in sorted (spatial) order.  pos = (x, y, z, R),
+// vel = (v, m), omg = (omega, I).
+struct ParticleBufs {
+  double4* pos;
+  double4* vel;
+  double4* omg;
+};
+
+// Neighbour list, one row per particle in wave-slab column-major layout:
+// entry (i, k) lives at ((i / 64) * max_nb + k) * 64 + i % 64.
+struct NbrList {
+  int* nbr;      // sorted index of the neighbour
+  double* hist;  // 3 planes of tangential overlap (x, y, z), stride cap
+  int* rowlen;
+  int64_t cap;   // entries per plane
+};
+
+// Particle-wall slots: slot s of particle i at s * n + i.
+struct WallSlots {
+  int* wid;      // wall id or -1
+  double* hist;  // 3 * kWallSlots planes of n
+};
+
+__host__ __device__ inline int64_t nbr_entry(int i, int k, int max_nb) {
+  return ((int64_t)(i >> 6) * max_nb + k) * 64 + (i & 63);
+}
+
+// ---------------------------------------------------------------- launches
+// Every launcher enqueues on `s` and returns the hipError_t of the launch.
+
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
+hipError_t launch_keys(const GridDev& g, const StepParams& sp, const double4* pos,
+                       const double4* vel, int* info, const double4* xref, int check_guard,
+                       uint32_t* keys, int* rank, int* count, int* flags, hipStream_t s);
+// exclusive scan of count[0..m) into start[0..m], start[m] = total
+hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums,
+                       hipStream_t s);
+hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const int* start,
+                          int* perm0, hipStream_t s);
+hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
+                            const int* start, const int* gid, int* perm, hipStream_t s);
+hipError_t launch_reorder(const StepParams& sp, const int* perm, ParticleBufs src,
+                          ParticleBufs dst, const int* gid_src, int* gid_dst,
+                          const int* info_src, int* info_dst, double4* xref,
+                          WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
+                          const double4* F_src, const double4* T_src, double4* F_dst,
+                          double4* T_dst, int* flags, hipStream_t s);
+hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
+                         const int* info, const int* start, const int* perm, NbrList old_l,
+                         NbrList new_l, int* flags, hipStream_t s);
+
+// force + integration kernels.  mode: 0 = velocity Verlet fused (second half
+// kick of this step, first half kick and drift of the next), 1 = velocity
+// Verlet last step of a call (second half kick, forces stored), 2 = explicit
+// Euler (forces at the current state, then the update; forces stored).
+hipError_t launch_force(int mode, int precision, const StepParams& sp, const PairCoef* pp,
+                        const PairCoef* pw, const WallDev* walls, ParticleBufs in,
+                        ParticleBufs out, const int* info, NbrList l, WallSlots ws,
+                        double4* F, double4* T, const int64_t* clock, int64_t step_rel,
+                        const int* flags, hipStream_t s);
+// first half kick + drift from stored forces (start of a velocity-Verlet call)
+hipError_t launch_kick_drift(const StepParams& sp, ParticleBufs st, const int* info,
+                             const double4* F, const double4* T, hipStream_t s);
+hipError_t launch_tick(int64_t* clock, int64_t k, hipStream_t s);
+// statistics: out[0] active, [1] list entries, [2] touching entries, [3] wall slots
+hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* info,
+                        NbrList l, WallSlots ws, unsigned long long* out, hipStream_t s);
+
+}  // namespace demgpu

@@ -1,0 +1,840 @@
+// HIP kernels (gfx950, wave64) of the soft-sphere DEM hot path.
+//
+// Method: Golshan et al., "Lethe-DEM" (arXiv 2106.09576).
+//   contact search   Sec. 3.2: particles sorted into cells, broad search over
+//                    a cell and its neighbour cells, fine search keeping pairs
+//                    closer than the threshold; rerun every K steps (Sec. 3.1)
+//   contact law      Sec. 2.1: Eqs. (deltan), (vecn), (delta_t), (vrt),
+//                    (normal_force), (tangential_force), (nonlinearkn)-
+//                    (nonlinearetat), effective-parameter table, (torque_t),
+//                    constant rolling model, (coulomb_overlap)-(coulomb_overlap3)
+//   walls            Sec. 2.1 last paragraph: same law against a wall
+//   integration      Sec. 2.2: Eqs. (integ_EE), (halfstep), (newvv)
+//
+// Design (MI355X): one thread per particle everywhere.  The force kernel is a
+// gather over each particle's full neighbour row, so every particle sums its
+// own forces in a fixed order (deterministic, no atomics).  Both directions of
+// a pair keep their own copy of the tangential overlap; the contact law is
+// written so that evaluating it from j's side gives exactly -F and -delta_t
+// (IEEE negation symmetry; this file is compiled without FP contraction), so
+// the two copies never drift apart.  Rows are stored column-major inside each
+// wavefront's slab, so every load of a neighbour index or history component is
+// one coalesced 64-lane access.  The force kernel also integrates its own
+// particle (ping-pong state buffers), so a time step is one launch.
+#include "dem_device.hpp"
+
+namespace demgpu {
+
+// ------------------------------------------------------------------ helpers
+
+// Blocks of a 1-D launch are spread over the 8 XCDs round-robin; remap so each
+// XCD works on a contiguous range of particles (neighbours then share its L2).
+__device__ inline int xcd_block() {
+  const unsigned nb = gridDim.x;
+  const unsigned b = blockIdx.x;
+  if ((nb & 7u) != 0u) return (int)b;
+  return (int)((b & 7u) * (nb >> 3) + (b >> 3));
+}
+
+static inline unsigned grid_for(int64_t n) {
+  int64_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  b = (b + 7) & ~int64_t(7);
+  return (unsigned)b;
+}
+
+__device__ inline bool finite3(double a, double b, double c) {
+  return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+__device__ inline uint32_t spread2(uint32_t v) { return (v & 1u) | ((v & 2u) << 2); }
+
+__device__ inline int cell_coord(double x, double lo, double h, int nc) {
+  int c = (int)floor((x - lo) / h);
+  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
+}
+
+__device__ inline uint32_t cell_key(const GridDev& g, int cx, int cy, int cz) {
+  uint32_t brick = ((uint32_t)(cz >> 2) * (uint32_t)g.nb[1] + (uint32_t)(cy >> 2)) *
+                       (uint32_t)g.nb[0] +
+                   (uint32_t)(cx >> 2);
+  uint32_t in = spread2(cx & 3) | (spread2(cy & 3) << 1) | (spread2(cz & 3) << 2);
+  return brick * 64u + in;
+}
+
+// ------------------------------------------------------------------ fill
+
+__global__ void k_fill_i32(int* p, int v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t b = (n + kBlock - 1) / kBlock;
+  unsigned nb = (unsigned)(b > 65536 ? 65536 : b);
+  hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- sort: keys
+
+// Cell key of every particle; deactivates particles outside the domain box,
+// checks the displacement guard and non-finite states, counts per cell (the
+// returned atomic slot is the particle's provisional rank in its cell).
+__global__ void k_keys(GridDev g, StepParams sp, const double4* __restrict__ pos,
+                       const double4* __restrict__ vel, int* __restrict__ info,
+                       const double4* __restrict__ xref, int check_guard,
+                       uint32_t* __restrict__ keys, int* __restrict__ rank,
+                       int* __restrict__ count, int* __restrict__ flags) {
+  int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= sp.n) return;
+  int inf = info[i];
+  uint32_t key = (uint32_t)g.n_keys;
+  if (!(inf & kInactive)) {
+    double4 p = pos[i];
+    double4 v = vel[i];
+    if (!finite3(p.x, p.y, p.z) || !finite3(v.x, v.y, v.z)) atomicOr(flags, kFlagNonFinite);
+    if (check_guard) {
+      double4 r = xref[i];
+      double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
+      double d2 = (dx * dx + dy * dy) + dz * dz;
+      if (d2 > sp.guard2) atomicOr(flags, kFlagGuard);
+    }
+    bool inside = p.x >= g.lo[0] && p.x < g.hi[0] && p.y >= g.lo[1] && p.y < g.hi[1] &&
+                  p.z >= g.lo[2] && p.z < g.hi[2];
+    if (!inside) {
+      info[i] = inf | kInactive;
+    } else {
+      int cx = cell_coord(p.x, g.lo[0], g.h, g.nc[0]);
+      int cy = cell_coord(p.y, g.lo[1], g.h, g.nc[1]);
+      int cz = cell_coord(p.z, g.lo[2], g.h, g.nc[2]);
+      key = cell_key(g, cx, cy, cz);
+    }
+  }
+  keys[i] = key;
+  rank[i] = atomicAdd(&count[key], 1);
+}
+
+hipError_t launch_keys(const GridDev& g, const StepParams& sp, const double4* pos,
+                       const double4* vel, int* info, const double4* xref, int check_guard,
+                       uint32_t* keys, int* rank, int* count, int* flags, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, g, sp, pos, vel, info,
+                     xref, check_guard, keys, rank, count, flags);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- sort: scan
+// Three-phase exclusive scan: tile sums, one-block scan of the tile sums,
+// tile-local scan plus offset.  Tiles of 1024 elements (256 threads x 4).
+
+constexpr int kScanTile = 1024;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
+  // 256 threads, 4 waves: wave-level inclusive scan via shuffles, then waves.
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[w] = x;
+  __syncthreads();
+  int wsum = 0;
+  for (int k = 0; k < w; ++k) wsum += sh[k];
+  int tot = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  *total = tot;
+  return x - v + wsum;
+}
+
+__global__ void k_scan_tiles(const int* __restrict__ in, int64_t m, int* __restrict__ tsum) {
+  __shared__ int sh[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (base + k < m) s += in[base + k];
+  int tot;
+  block_exclusive_scan(s, sh, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(int* __restrict__ tsum, int64_t nt) {
+  __shared__ int sh[4];
+  int carry = 0;
+  for (int64_t base = 0; base < nt; base += kBlock) {
+    int64_t i = base + threadIdx.x;
+    int v = i < nt ? tsum[i] : 0;
+    int tot;
+    int ex = block_exclusive_scan(v, sh, &tot);
+    if (i < nt) tsum[i] = ex + carry;
+    carry += tot;
+  }
+}
+
+__global__ void k_scan_apply(const int* __restrict__ in, int64_t m, const int* __restrict__ tsum,
+                             int* __restrict__ out) {
+  __shared__ int sh[4];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+  int v[4];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < m) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int tot;
+  int ex = block_exclusive_scan(s, sh, &tot) + tsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < m) out[base + k] = ex;
+    ex += v[k];
+  }
+  // the element after the last one holds the total
+  if (base <= m - 1 && m - 1 < base + 4) out[m] = ex;
+}
+
+hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums,
+                       hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  int64_t nt = (m + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kBlock), 0, s, count, m, tile_sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tile_sums, nt);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kBlock), 0, s, count, m, tile_sums,
+                     start);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- sort: scatter
+
+__global__ void k_scatter(int n, const uint32_t* __restrict__ keys, const int* __restrict__ rank,
+                          const int* __restrict__ start, int* __restrict__ perm0) {
+  int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  perm0[start[keys[i]] + rank[i]] = i;
+}
+
+hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const int* start,
+                          int* perm0, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n)), dim3(kBlock), 0, s, n, keys, rank, start,
+                     perm0);
+  return hipGetLastError();
+}
+
+// Within a cell, order particles by gid so the sorted order (and with it every
+// summation order) is independent of atomic arrival order.  Inactive particles
+// (last key) keep their arrival order: they take part in no computation.
+__global__ void k_cell_rank(int n, uint32_t n_keys, const int* __restrict__ perm0,
+                            const uint32_t* __restrict__ keys, const int* __restrict__ start,
+                            const int* __restrict__ gid, int* __restrict__ perm) {
+  int p = xcd_block() * kBlock + threadIdx.x;
+  if (p >= n) return;
+  int o = perm0[p];
+  uint32_t k = keys[o];
+  if (k == n_keys) {
+    perm[p] = o;
+    return;
+  }
+  int s = start[k], e = start[k + 1];
+  int g = gid[o];
+  int r = 0;
+  for (int q = s; q < e; ++q) r += gid[perm0[q]] < g ? 1 : 0;
+  perm[s + r] = o;
+}
+
+hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
+                            const int* start, const int* gid, int* perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cell_rank, dim3(grid_for(n)), dim3(kBlock), 0, s, n, (uint32_t)n_keys,
+                     perm0, keys, start, gid, perm);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ walls
+
+// Candidate / touching predicates of particle centre x (radius R) against a
+// wall, evaluated without square roots; when touching also the unit normal
+// from the particle to the wall, the overlap and the contact point.
+struct WallGeo {
+  bool candidate, touching;
+  double n[3], dn, xc[3];
+};
+
+__device__ inline double dot3(const double* a, const double* b) {
+  return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2];
+}
+
+__device__ inline void wall_geo(const WallDev& W, const double x[3], double R, double skin,
+                                bool need_contact, WallGeo& g) {
+  g.candidate = false;
+  g.touching = false;
+  double rel[3] = {x[0] - W.p[0], x[1] - W.p[1], x[2] - W.p[2]};
+  if (W.kind == 0) {
+    double dist = dot3(rel, W.nrm);
+    if (W.bounded) {
+      double a = dot3(rel, W.u), b = dot3(rel, W.vax);
+      if (!(fabs(a) <= W.hu && fabs(b) <= W.hv)) return;
+    }
+    g.candidate = (dist < R + skin) && (dist > -R);
+    g.touching = dist < R;
+    if (g.touching && need_contact) {
+      for (int k = 0; k < 3; ++k) {
+        g.n[k] = -W.nrm[k];
+        g.xc[k] = x[k] - dist * W.nrm[k];
+      }
+      g.dn = R - dist;
+    }
+    return;
+  }
+  double sax = dot3(rel, W.nrm);
+  if (!(sax >= W.smin && sax <= W.smax)) return;
+  double r[3] = {rel[0] - sax * W.nrm[0], rel[1] - sax * W.nrm[1], rel[2] - sax * W.nrm[2]};
+  double rho2 = dot3(r, r);
+  if (!(rho2 > 0.0)) return;
+  const double Rc = W.radius;
+  if (W.inside) {
+    double lo = Rc - (R + skin);
+    double hi = Rc + R;
+    bool above = (lo <= 0.0) || (rho2 > lo * lo);
+    g.candidate = above && (rho2 < hi * hi);
+    double lt = Rc - R;
+    g.touching = (lt <= 0.0) || (rho2 > lt * lt);
+  } else {
+    double hi = Rc + R + skin;
+    double lo = Rc - R;
+    bool above = (lo <= 0.0) || (rho2 > lo * lo);
+    g.candidate = above && (rho2 < hi * hi);
+    double lt = Rc + R;
+    g.touching = rho2 < lt * lt;
+  }
+  if (g.touching && need_contact) {
+    double rho = sqrt(rho2);
+    double er[3] = {r[0] / rho, r[1] / rho, r[2] / rho};
+    double dist = W.inside ? (Rc - rho) : (rho - Rc);
+    g.dn = R - dist;
+    for (int k = 0; k < 3; ++k) {
+      g.n[k] = W.inside ? er[k] : -er[k];
+      g.xc[k] = W.p[k] + sax * W.nrm[k] + Rc * er[k];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- reorder
+
+// Gather every particle array into sorted order, record the reference
+// position of the displacement guard, and redo the particle-wall search at
+// the new position carrying the tangential overlap of walls already listed.
+__global__ void k_reorder(StepParams sp, const int* __restrict__ perm, ParticleBufs src,
+                          ParticleBufs dst, const int* __restrict__ gid_src,
+                          int* __restrict__ gid_dst, const int* __restrict__ info_src,
+                          int* __restrict__ info_dst, double4* __restrict__ xref,
+                          WallSlots ws_src, WallSlots ws_dst, const WallDev* __restrict__ walls,
+                          const double4* __restrict__ F_src, const double4* __restrict__ T_src,
+                          double4* __restrict__ F_dst, double4* __restrict__ T_dst,
+                          int* __restrict__ flags) {
+  int p = xcd_block() * kBlock + threadIdx.x;
+  const int n = sp.n;
+  if (p >= n) return;
+  int o = perm[p];
+  double4 ps = src.pos[o];
+  dst.pos[p] = ps;
+  dst.vel[p] = src.vel[o];
+  dst.omg[p] = src.omg[o];
+  gid_dst[p] = gid_src[o];
+  int inf = info_src[o];
+  info_dst[p] = inf;
+  xref[p] = ps;
+  if (F_src) {
+    F_dst[p] = F_src[o];
+    T_dst[p] = T_src[o];
+  }
+  int c = 0;
+  if (!(inf & kInactive)) {
+    double x[3] = {ps.x, ps.y, ps.z};
+    for (int w = 0; w < sp.n_walls; ++w) {
+      WallGeo g;
+      wall_geo(walls[w], x, ps.w, sp.skin, false, g);
+      if (!g.candidate) continue;
+      if (c == kWallSlots) {
+        atomicOr(flags, kFlagWallOverflow);
+        break;
+      }
+      double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+      for (int s = 0; s < kWallSlots; ++s) {
+        int ow = ws_src.wid[(int64_t)s * n + o];
+        if (ow < 0) break;
+        if (ow == w) {
+          h0 = ws_src.hist[(int64_t)(3 * s + 0) * n + o];
+          h1 = ws_src.hist[(int64_t)(3 * s + 1) * n + o];
+          h2 = ws_src.hist[(int64_t)(3 * s + 2) * n + o];
+          break;
+        }
+      }
+      ws_dst.wid[(int64_t)c * n + p] = w;
+      ws_dst.hist[(int64_t)(3 * c + 0) * n + p] = h0;
+      ws_dst.hist[(int64_t)(3 * c + 1) * n + p] = h1;
+      ws_dst.hist[(int64_t)(3 * c + 2) * n + p] = h2;
+      ++c;
+    }
+  }
+  for (; c < kWallSlots; ++c) ws_dst.wid[(int64_t)c * n + p] = -1;
+}
+
+hipError_t launch_reorder(const StepParams& sp, const int* perm, ParticleBufs src,
+                          ParticleBufs dst, const int* gid_src, int* gid_dst,
+                          const int* info_src, int* info_dst, double4* xref,
+                          WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
+                          const double4* F_src, const double4* T_src, double4* F_dst,
+                          double4* T_dst, int* flags, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, perm, src, dst,
+                     gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, F_src,
+                     T_src, F_dst, T_dst, flags);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ search
+
+// Broad + fine search for particle p (sorted order): scan its own and the 26
+// surrounding cells, keep q != p with |x_q - x_p|^2 < r_s^2 (evaluated in a
+// fixed order without fused operations), and carry the
+// tangential overlap of pairs that were already listed: the old row of p is
+// found through the sort permutation (old index of p and q).
+__global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ pos,
+                         const int* __restrict__ info, const int* __restrict__ start,
+                         const int* __restrict__ perm, NbrList old_l, NbrList new_l,
+                         int* __restrict__ flags) {
+  int p = xcd_block() * kBlock + threadIdx.x;
+  if (p >= sp.n) return;
+  const int max_nb = sp.max_nb;
+  if (info[p] & kInactive) {
+    new_l.rowlen[p] = 0;
+    return;
+  }
+  double4 pp = pos[p];
+  int cx = cell_coord(pp.x, g.lo[0], g.h, g.nc[0]);
+  int cy = cell_coord(pp.y, g.lo[1], g.h, g.nc[1]);
+  int cz = cell_coord(pp.z, g.lo[2], g.h, g.nc[2]);
+  const int op = perm[p];
+  const int olen = old_l.rowlen[op];
+  int cnt = 0;
+  bool overflow = false;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int z = cz + dz;
+    if (z < 0 || z >= g.nc[2]) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int y = cy + dy;
+      if (y < 0 || y >= g.nc[1]) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        int x = cx + dx;
+        if (x < 0 || x >= g.nc[0]) continue;
+        uint32_t key = cell_key(g, x, y, z);
+        int s = start[key], e = start[key + 1];
+        for (int q = s; q < e; ++q) {
+          if (q == p) continue;
+          double4 pq = pos[q];
+          double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
+          double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+          if (!(d2 < sp.rs2)) continue;
+          if (cnt == max_nb) {
+            overflow = true;
+            continue;
+          }
+          const int oq = perm[q];
+          double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+          for (int k = 0; k < olen; ++k) {
+            int64_t oe = nbr_entry(op, k, max_nb);
+            if (old_l.nbr[oe] == oq) {
+              h0 = old_l.hist[oe];
+              h1 = old_l.hist[old_l.cap + oe];
+              h2 = old_l.hist[2 * old_l.cap + oe];
+              break;
+            }
+          }
+          int64_t ne = nbr_entry(p, cnt, max_nb);
+          new_l.nbr[ne] = q;
+          new_l.hist[ne] = h0;
+          new_l.hist[new_l.cap + ne] = h1;
+          new_l.hist[2 * new_l.cap + ne] = h2;
+          ++cnt;
+        }
+      }
+    }
+  }
+  if (overflow) atomicOr(flags, kFlagNbrOverflow);
+  new_l.rowlen[p] = cnt;
+}
+
+hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
+                         const int* info, const int* start, const int* perm, NbrList old_l,
+                         NbrList new_l, int* flags, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_search, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, g, sp, pos, info,
+                     start, perm, old_l, new_l, flags);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- contact law
+
+// The Hertz-Mindlin law in arithmetic type R (double: plain FP64; float: the
+// constitutive part in FP32 with geometry, history and sums in FP64).
+// Inputs: overlap dn >= 0, unit normal n (from body i to body j), contact
+// relative velocity vij, wrel = omega_i - omega_j, effective mass and radius,
+// lever arm Ri, pair coefficients; the tangential overlap dtl (FP64) is
+// updated in place.  Output: force on i and torque on i.
+template <typename R>
+__device__ inline void hertz_mindlin(const PairCoef& c, int rolling, double dt, R dn,
+                                     const R n[3], const R vij[3], const R wrel[3], R me,
+                                     R Re, R Ri, double dtl[3], double Fi[3], double Mi[3]) {
+  R vn = (vij[0] * n[0] + vij[1] * n[1]) + vij[2] * n[2];
+  R vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
+  R vrt[3] = {vij[0] - vrn[0], vij[1] - vrn[1], vij[2] - vrn[2]};
+  // Eq. (delta_t): the history stays in FP64
+  for (int k = 0; k < 3; ++k) dtl[k] = dtl[k] + (double)vrt[k] * dt;
+  R dt3[3] = {(R)dtl[0], (R)dtl[1], (R)dtl[2]};
+
+  const R Ye = (R)c.Ye, Ge = (R)c.Ge, ceta = (R)c.ceta, mu = (R)c.mu;
+  R q = sqrt(Re * dn);
+  R kn = (R)(4.0 / 3.0) * Ye * q;
+  R kt = (R)8.0 * Ge * q;
+  R Sn = (R)2.0 * Ye * q;
+  R St = (R)8.0 * Ge * q;
+  R etan = ceta * sqrt(Sn * me);
+  R etat = ceta * sqrt(St * me);
+  R Fn[3], Ft[3];
+  for (int k = 0; k < 3; ++k) {
+    Fn[k] = -(kn * dn) * n[k] - etan * vrn[k];
+    Ft[k] = -(kt * dt3[k]) - etat * vrt[k];
+  }
+  R fn = sqrt((Fn[0] * Fn[0] + Fn[1] * Fn[1]) + Fn[2] * Fn[2]);
+  R ft = sqrt((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
+  if (ft >= mu * fn && ft > (R)0) {
+    for (int k = 0; k < 3; ++k) {
+      R fhat = mu * fn * Ft[k] / ft;
+      R ftilde = fhat + etat * vrt[k];
+      dtl[k] = (double)(ftilde / (-kt));
+      Ft[k] = fhat;
+    }
+  }
+  R nx[3] = {n[1] * Ft[2] - n[2] * Ft[1], n[2] * Ft[0] - n[0] * Ft[2],
+             n[0] * Ft[1] - n[1] * Ft[0]};
+  R Mr[3] = {(R)0, (R)0, (R)0};
+  if (rolling == 1) {
+    R wn = sqrt((wrel[0] * wrel[0] + wrel[1] * wrel[1]) + wrel[2] * wrel[2]);
+    if (wn > (R)0) {
+      R mur = (R)c.mur;
+      for (int k = 0; k < 3; ++k) Mr[k] = -mur * Re * fn * (wrel[k] / wn);
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    Fi[k] = (double)(Fn[k] + Ft[k]);
+    Mi[k] = (double)(Ri * nx[k] + Mr[k]);
+  }
+}
+
+// Particle i against neighbour j, evaluated from i's side.  Returns the force
+// and torque on i; dtl is the history of the directed pair (i -> j).
+template <typename R>
+__device__ inline void pp_contact(const PairCoef& c, int rolling, double dt, double4 xi,
+                                  double4 vi, double4 wi, double4 xj, double4 vj, double4 wj,
+                                  double dtl[3], double Fi[3], double Mi[3]) {
+  double dx[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
+  double d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+  double rsum = xi.w + xj.w;
+  if (!(d2 < rsum * rsum)) {
+    dtl[0] = dtl[1] = dtl[2] = 0.0;
+    Fi[0] = Fi[1] = Fi[2] = 0.0;
+    Mi[0] = Mi[1] = Mi[2] = 0.0;
+    return;
+  }
+  double d = sqrt(d2);
+  double dn = rsum - d;
+  if (dn < 0.0) dn = 0.0;
+  double nd[3] = {dx[0] / d, dx[1] / d, dx[2] / d};
+  const double Ri = xi.w, Rj = xj.w;
+  double rw[3] = {Ri * wi.x + Rj * wj.x, Ri * wi.y + Rj * wj.y, Ri * wi.z + Rj * wj.z};
+  double rwxn[3] = {rw[1] * nd[2] - rw[2] * nd[1], rw[2] * nd[0] - rw[0] * nd[2],
+                    rw[0] * nd[1] - rw[1] * nd[0]};
+  double vd[3] = {(vi.x - vj.x) + rwxn[0], (vi.y - vj.y) + rwxn[1], (vi.z - vj.z) + rwxn[2]};
+  double wd[3] = {wi.x - wj.x, wi.y - wj.y, wi.z - wj.z};
+  double me = 1.0 / (1.0 / vi.w + 1.0 / vj.w);
+  double Re = 1.0 / (1.0 / Ri + 1.0 / Rj);
+  R n[3] = {(R)nd[0], (R)nd[1], (R)nd[2]};
+  R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
+  R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
+  hertz_mindlin<R>(c, rolling, dt, (R)dn, n, vij, wrel, (R)me, (R)Re, (R)Ri, dtl, Fi, Mi);
+}
+
+template <typename R>
+__device__ inline void pw_contact(const PairCoef& c, int rolling, double dt, const WallDev& W,
+                                  double skin, double4 xi, double4 vi, double4 wi,
+                                  double dtl[3], double Fi[3], double Mi[3]) {
+  double x[3] = {xi.x, xi.y, xi.z};
+  WallGeo g;
+  wall_geo(W, x, xi.w, skin, true, g);
+  if (!g.touching) {
+    dtl[0] = dtl[1] = dtl[2] = 0.0;
+    Fi[0] = Fi[1] = Fi[2] = 0.0;
+    Mi[0] = Mi[1] = Mi[2] = 0.0;
+    return;
+  }
+  double dn = g.dn < 0.0 ? 0.0 : g.dn;
+  double arm[3] = {g.xc[0] - W.ax[0], g.xc[1] - W.ax[1], g.xc[2] - W.ax[2]};
+  double vw[3] = {W.omega[1] * arm[2] - W.omega[2] * arm[1],
+                  W.omega[2] * arm[0] - W.omega[0] * arm[2],
+                  W.omega[0] * arm[1] - W.omega[1] * arm[0]};
+  const double Ri = xi.w;
+  double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
+  double rwxn[3] = {rw[1] * g.n[2] - rw[2] * g.n[1], rw[2] * g.n[0] - rw[0] * g.n[2],
+                    rw[0] * g.n[1] - rw[1] * g.n[0]};
+  double vd[3] = {(vi.x - vw[0]) + rwxn[0], (vi.y - vw[1]) + rwxn[1], (vi.z - vw[2]) + rwxn[2]};
+  double wd[3] = {wi.x - W.omega[0], wi.y - W.omega[1], wi.z - W.omega[2]};
+  R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
+  R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
+  R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
+  hertz_mindlin<R>(c, rolling, dt, (R)dn, n, vij, wrel, (R)vi.w, (R)Ri, (R)Ri, dtl, Fi, Mi);
+}
+
+// ------------------------------------------------------------------- force
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
+        const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
+        const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
+        double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
+        const int* __restrict__ flags) {
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  const int n = sp.n;
+  if (i >= n) return;
+  double4 xi = in.pos[i];
+  double4 vi = in.vel[i];
+  double4 wi = in.omg[i];
+  const int inf = info[i];
+  // frozen after an error, and for inactive particles: carry the state over
+  if ((inf & kInactive) || *flags != 0) {
+    out.pos[i] = xi;
+    out.vel[i] = vi;
+    out.omg[i] = wi;
+    if (MODE != 0) {
+      Fo[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+      To[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+    return;
+  }
+  const int ti = inf & kTypeMask;
+  const double dt = sp.dt;
+  double F[3] = {0.0, 0.0, 0.0};
+  double T[3] = {0.0, 0.0, 0.0};
+  const int len = l.rowlen[i];
+  const int max_nb = sp.max_nb;
+  for (int k = 0; k < len; ++k) {
+    const int64_t e = nbr_entry(i, k, max_nb);
+    const int j = l.nbr[e];
+    double4 xj = in.pos[j];
+    double4 vj = in.vel[j];
+    double4 wj = in.omg[j];
+    const int tj = info[j] & kTypeMask;
+    double dtl[3] = {l.hist[e], l.hist[l.cap + e], l.hist[2 * l.cap + e]};
+    double Fi[3], Mi[3];
+    pp_contact<R>(ppc[ti * kMaxTypes + tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+    l.hist[e] = dtl[0];
+    l.hist[l.cap + e] = dtl[1];
+    l.hist[2 * l.cap + e] = dtl[2];
+    F[0] += Fi[0];
+    F[1] += Fi[1];
+    F[2] += Fi[2];
+    T[0] += Mi[0];
+    T[1] += Mi[1];
+    T[2] += Mi[2];
+  }
+  // walls: time of this force evaluation
+  const double t = (double)(*clock + step_rel) * dt;
+  for (int s = 0; s < kWallSlots; ++s) {
+    const int w = ws.wid[(int64_t)s * n + i];
+    if (w < 0) break;
+    const WallDev& W = walls[w];
+    double dtl[3] = {ws.hist[(int64_t)(3 * s) * n + i], ws.hist[(int64_t)(3 * s + 1) * n + i],
+                     ws.hist[(int64_t)(3 * s + 2) * n + i]};
+    double Fi[3], Mi[3];
+    if (t >= W.t_on && t < W.t_off) {
+      pw_contact<R>(pwc[ti * kMaxTypes + W.material], sp.rolling, dt, W, sp.skin, xi, vi, wi,
+                    dtl, Fi, Mi);
+    } else {
+      dtl[0] = dtl[1] = dtl[2] = 0.0;
+      Fi[0] = Fi[1] = Fi[2] = 0.0;
+      Mi[0] = Mi[1] = Mi[2] = 0.0;
+    }
+    ws.hist[(int64_t)(3 * s) * n + i] = dtl[0];
+    ws.hist[(int64_t)(3 * s + 1) * n + i] = dtl[1];
+    ws.hist[(int64_t)(3 * s + 2) * n + i] = dtl[2];
+    F[0] += Fi[0];
+    F[1] += Fi[1];
+    F[2] += Fi[2];
+    T[0] += Mi[0];
+    T[1] += Mi[1];
+    T[2] += Mi[2];
+  }
+  // integration of particle i
+  const double m = vi.w, I = wi.w;
+  double a[3] = {F[0] / m + sp.g[0], F[1] / m + sp.g[1], F[2] / m + sp.g[2]};
+  double al[3] = {T[0] / I, T[1] / I, T[2] / I};
+  if (MODE == 2) {
+    // explicit Euler, Eq. (integ_EE): x with the old velocity
+    xi.x = xi.x + vi.x * dt;
+    xi.y = xi.y + vi.y * dt;
+    xi.z = xi.z + vi.z * dt;
+    vi.x = vi.x + a[0] * dt;
+    vi.y = vi.y + a[1] * dt;
+    vi.z = vi.z + a[2] * dt;
+    wi.x = wi.x + al[0] * dt;
+    wi.y = wi.y + al[1] * dt;
+    wi.z = wi.z + al[2] * dt;
+  } else {
+    const double h = sp.hdt;
+    // second half kick of this step, Eq. (newvv)
+    vi.x = vi.x + a[0] * h;
+    vi.y = vi.y + a[1] * h;
+    vi.z = vi.z + a[2] * h;
+    wi.x = wi.x + al[0] * h;
+    wi.y = wi.y + al[1] * h;
+    wi.z = wi.z + al[2] * h;
+    if (MODE == 0) {
+      // first half kick and drift of the next step, Eq. (halfstep)
+      vi.x = vi.x + a[0] * h;
+      vi.y = vi.y + a[1] * h;
+      vi.z = vi.z + a[2] * h;
+      wi.x = wi.x + al[0] * h;
+      wi.y = wi.y + al[1] * h;
+      wi.z = wi.z + al[2] * h;
+      xi.x = xi.x + vi.x * dt;
+      xi.y = xi.y + vi.y * dt;
+      xi.z = xi.z + vi.z * dt;
+    }
+  }
+  out.pos[i] = xi;
+  out.vel[i] = vi;
+  out.omg[i] = wi;
+  if (MODE != 0) {
+    Fo[i] = make_double4(F[0], F[1], F[2], 0.0);
+    To[i] = make_double4(T[0], T[1], T[2], 0.0);
+  }
+}
+
+hipError_t launch_force(int mode, int precision, const StepParams& sp, const PairCoef* pp,
+                        const PairCoef* pw, const WallDev* walls, ParticleBufs in,
+                        ParticleBufs out, const int* info, NbrList l, WallSlots ws,
+                        double4* F, double4* T, const int64_t* clock, int64_t step_rel,
+                        const int* flags, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  dim3 gr(grid_for(sp.n)), bl(kBlock);
+#define DEM_LAUNCH(RT, M)                                                                   \
+  hipLaunchKernelGGL((k_force<RT, M>), gr, bl, 0, s, sp, pp, pw, walls, in, out, info, l, ws, \
+                     F, T, clock, step_rel, flags)
+  if (precision == 0) {
+    if (mode == 0) DEM_LAUNCH(double, 0);
+    else if (mode == 1) DEM_LAUNCH(double, 1);
+    else DEM_LAUNCH(double, 2);
+  } else {
+    if (mode == 0) DEM_LAUNCH(float, 0);
+    else if (mode == 1) DEM_LAUNCH(float, 1);
+    else DEM_LAUNCH(float, 2);
+  }
+#undef DEM_LAUNCH
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ kick-drift, clock
+
+__global__ void k_kick_drift(StepParams sp, ParticleBufs st, const int* __restrict__ info,
+                             const double4* __restrict__ F, const double4* __restrict__ T) {
+  int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= sp.n) return;
+  if (info[i] & kInactive) return;
+  double4 x = st.pos[i], v = st.vel[i], w = st.omg[i];
+  double4 f = F[i], tq = T[i];
+  const double h = sp.hdt, dt = sp.dt;
+  double a0 = f.x / v.w + sp.g[0], a1 = f.y / v.w + sp.g[1], a2 = f.z / v.w + sp.g[2];
+  v.x = v.x + a0 * h;
+  v.y = v.y + a1 * h;
+  v.z = v.z + a2 * h;
+  w.x = w.x + (tq.x / w.w) * h;
+  w.y = w.y + (tq.y / w.w) * h;
+  w.z = w.z + (tq.z / w.w) * h;
+  x.x = x.x + v.x * dt;
+  x.y = x.y + v.y * dt;
+  x.z = x.z + v.z * dt;
+  st.pos[i] = x;
+  st.vel[i] = v;
+  st.omg[i] = w;
+}
+
+hipError_t launch_kick_drift(const StepParams& sp, ParticleBufs st, const int* info,
+                             const double4* F, const double4* T, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, st, info, F, T);
+  return hipGetLastError();
+}
+
+__global__ void k_tick(int64_t* clock, int64_t k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += k;
+}
+
+hipError_t launch_tick(int64_t* clock, int64_t k, hipStream_t s) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(64), 0, s, clock, k);
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------------- stats
+
+__global__ void k_stats(StepParams sp, const double4* __restrict__ pos,
+                        const int* __restrict__ info, NbrList l, WallSlots ws,
+                        unsigned long long* out) {
+  int i = blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long a = 0, e = 0, tch = 0, wc = 0;
+  if (i < sp.n && !(info[i] & kInactive)) {
+    a = 1;
+    double4 xi = pos[i];
+    int len = l.rowlen[i];
+    e = (unsigned long long)len;
+    for (int k = 0; k < len; ++k) {
+      int j = l.nbr[nbr_entry(i, k, sp.max_nb)];
+      double4 xj = pos[j];
+      double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+      double d2 = (dx * dx + dy * dy) + dz * dz;
+      double rs = xi.w + xj.w;
+      if (d2 < rs * rs) ++tch;
+    }
+    for (int s = 0; s < kWallSlots; ++s)
+      if (ws.wid[(int64_t)s * sp.n + i] >= 0) ++wc;
+  }
+  // wave reduction, then one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    e += __shfl_down(e, o, 64);
+    tch += __shfl_down(tch, o, 64);
+    wc += __shfl_down(wc, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&out[0], a);
+    atomicAdd(&out[1], e);
+    atomicAdd(&out[2], tch);
+    atomicAdd(&out[3], wc);
+  }
+}
+
+hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* info, NbrList l,
+                        WallSlots ws, unsigned long long* out, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  unsigned nb = (unsigned)((sp.n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_stats, dim3(nb), dim3(kBlock), 0, s, sp, pos, info, l, ws, out);
+  return hipGetLastError();
+}
+
+}  // namespace demgpu
