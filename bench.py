@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Benchmark of the DEM hot path on one MI355X: particle-steps/s at 1M spheres.
+
+Workload: the rotating drum of 1,000,000 monodisperse spheres (d = 3 mm,
+rho = 2500 kg/m^3, E = 1 MPa, nu = 0.3, e = 0.8, mu_s = 0.5, mu_r = 0.2),
+spinning at 1 rad/s about its horizontal axis with two co-rotating end walls,
+dt = 5e-6 s, contact search every 20 steps, r_s = 1.3 d.  The drum is R =
+0.2205 m, L = 0.441 m so that the spheres form a 35 % bulk fill (the
+0.15 m x 0.3 m drum cannot hold 1M spheres of 3 mm).  Inputs are synthetic
+(seeded lattice placement, no dataset), resident in HBM before timing.
+
+One step = contact search (every 20th step) + particle-particle and
+particle-wall Hertz-Mindlin forces with tangential history + velocity-Verlet
+integration, all in the library's HIP kernels.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s at 1M spheres (+% HBM roofline), batched FP32/FP64 vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes of one force+integration launch (the dominant kernel):
+# per active particle 72 B state read + 72 B state written + 8 B radius/material,
+# per unordered candidate pair 8 B identity + 24 B history read + 24 B written
+BYTES_PER_PARTICLE = 152.0
+BYTES_PER_PAIR = 56.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("dem_kernels.hip", "dem_device.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2106_09576_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(precision):
+    """HBM bytes per force launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "force_kernel_traffic_drum1m.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    e = d.get("per_launch_bytes", {}).get(precision)
+    return None if e is None else float(e)
+
+
+def measure(args, precision, scene):
+    import torch
+    from paper_2106_09576_amd import Dem
+
+    log(f"{precision}: uploading {scene['particles']['pos'].shape[0]} particles")
+    sim = Dem.from_scene(scene, precision=precision)
+    stream = torch.cuda.ExternalStream(sim.stream())
+    log(f"{precision}: warmup {args.warmup} steps (drum settles, contacts form)")
+    done = 0
+    while done < args.warmup:
+        k = min(args.warmup - done, 5000)
+        sim.step(k)
+        done += k
+        log(f"{precision}: warmup {done}/{args.warmup}")
+    torch.cuda.synchronize()
+    st0 = sim.get_stats()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    log(f"{precision}: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    st1 = sim.get_stats()
+    n_active = 0.5 * (st0["n_active"] + st1["n_active"])
+    pairs = 0.25 * (st0["n_list_entries"] + st1["n_list_entries"])
+    touching = 0.25 * (st0["n_touching"] + st1["n_touching"])
+    # per-kernel durations with HIP events (eager launches, same kernels)
+    n_t = min(args.steps, 200)
+    sim.set_timing(True)
+    sim.step(n_t)
+    tm = sim.get_timing()
+    sim.set_timing(False)
+    force_ms = tm["force_ms"] / max(tm["force_launches"], 1)
+    search_ms = tm["search_ms"] / max(tm["searches"], 1)
+    algo_bytes = BYTES_PER_PARTICLE * n_active + BYTES_PER_PAIR * pairs
+    achieved = algo_bytes / (force_ms * 1e-3) / 1e9
+    res = dict(
+        precision=precision,
+        value=n_active * args.steps / wall,
+        ms_per_step=1e3 * wall / args.steps,
+        event_ms_per_step=ev_ms / args.steps,
+        n_active=int(n_active),
+        pairs_per_particle=pairs / max(n_active, 1),
+        touching_per_particle=touching / max(n_active, 1),
+        contacts_per_s=touching * args.steps / wall,
+        force_kernel_ms=force_ms,
+        search_ms=search_ms,
+        force_kernel_algo_bytes=algo_bytes,
+        force_kernel_gbs=achieved,
+        wall_candidates=st1["n_wall_candidates"],
+        rebuilds_timed=int(st1["n_rebuilds"] - st0["n_rebuilds"]),
+        device_gib=st1["device_bytes"] / 2 ** 30,
+        max_neighbors=st1["max_neighbors"],
+    )
+    log(f"{precision}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step, "
+        f"force kernel {force_ms:.4f} ms ({achieved:.0f} GB/s algorithmic)")
+    sim.close()
+    return res
+
+
+def cpu_baseline(args, scene):
+    """The FP64 oracle (plain C, single thread) on a bounded sample: the same
+    1M-sphere drum from its initial state, a few steps including one search."""
+    from oracle import oracle_from_scene
+    log("cpu baseline: building oracle (initial search)")
+    o = oracle_from_scene(scene)
+    steps = args.cpu_steps
+    log(f"cpu baseline: timing {steps} oracle steps")
+    t0 = time.perf_counter()
+    o.step(steps)
+    t1 = time.perf_counter()
+    n = scene["particles"]["pos"].shape[0]
+    sample = (f"FP64 oracle, 1 thread, same 1M-sphere drum from its initial lattice state, "
+              f"steps 1-{steps} (search at step 20), {t1 - t0:.1f} s")
+    return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle", "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=20000)
+    ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 device copies of 1 GiB (read 1 GiB, write 1 GiB each), "
+                         "to scale the FETCH_SIZE / WRITE_SIZE counters")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = (1 << 30) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration done: 5 x (1 GiB read + 1 GiB written)")
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU domain "
+              f"decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs the GPU", file=sys.stderr)
+        sys.exit(1)
+    import workloads as W
+    log(f"building drum scene, n = {args.n}")
+    scene = W.drum_scene(n=args.n)
+    geo = scene["geometry"]
+    precs = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
+    results = {p: measure(args, p, scene) for p in precs}
+    main_p = "fp64" if "fp64" in results else precs[0]
+    r = results[main_p]
+    traffic = load_traffic(main_p)
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_p == "fp64" else "f32 law / f64 state",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"rotating drum, {args.n} spheres d=3mm, R={geo['R']:.4f} m, "
+                         f"L={geo['L']:.4f} m, 1 rad/s, dt=5e-6 s, search every 20 steps, "
+                         f"r_s=1.3 d, after {args.warmup} settling steps"),
+            "n_particles": args.n,
+            "pairs_per_particle": round(r["pairs_per_particle"], 3),
+            "touching_per_particle": round(r["touching_per_particle"], 3),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_force (contact law + integration, one launch per step)",
+            "achieved": r["force_kernel_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": r["force_kernel_gbs"] / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "force_kernel_ms": r["force_kernel_ms"],
+            "algo_bytes_per_launch": r["force_kernel_algo_bytes"],
+        },
+        "contacts_per_s": r["contacts_per_s"],
+        "results": results,
+    }
+    if "fp32" in results and "fp64" in results:
+        out["mixed_vs_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(args, scene)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

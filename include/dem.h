@@ -93,7 +93,7 @@ typedef struct {
   int32_t max_neighbors;   /* capacity per particle in use                  */
   int32_t precision;
   double r_s, cell_size, skin, d_max;
-  int64_t n_cells;         /* cells of the grid (padded to 4x4x4 bricks)    */
+  int64_t n_cells;         /* cell keys of the grid (Morton-padded)          */
   int64_t device_bytes;    /* device memory held by the context             */
 } dem_stats;
 

@@ -71,7 +71,7 @@ struct dem_ctx {
   int* rowlen[2]{};
   uint32_t* keys = nullptr;
   int *rank = nullptr, *count = nullptr, *start = nullptr, *tile_sums = nullptr;
-  int *perm0 = nullptr, *perm = nullptr;
+  int *perm0 = nullptr, *perm = nullptr, *inv = nullptr;
   PairCoef *d_pp = nullptr, *d_pw = nullptr;
   WallDev* d_walls = nullptr;
   int* d_flags = nullptr;
@@ -178,6 +178,19 @@ double damping_factor(double e) {
   return -2.0 * sqrt(5.0 / 6.0) * beta;
 }
 
+PairCoef make_coef(double Ye, double Ge, double e, double mu, double mur) {
+  PairCoef q;
+  memset(&q, 0, sizeof(q));
+  const double ceta = damping_factor(e);
+  q.kn = 4.0 / 3.0 * Ye;
+  q.kt = 8.0 * Ge;
+  q.en = ceta * sqrt(2.0 * Ye);
+  q.et = ceta * sqrt(8.0 * Ge);
+  q.mu = mu;
+  q.mur = mur;
+  return q;
+}
+
 // ------------------------------------------------------------ kernel groups
 
 ParticleBufs pbufs(dem_ctx* c, int k) { return ParticleBufs{c->pos[k], c->vel[k], c->omg[k]}; }
@@ -196,13 +209,14 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
   HIPCHK(launch_scatter(c->n, c->keys, c->rank, c->start, c->perm0, s));
   HIPCHK(launch_cell_rank(c->n, c->grid.n_keys, c->perm0, c->keys, c->start, c->gid[p],
                           c->perm, s));
-  HIPCHK(launch_reorder(c->sp, c->perm, pbufs(c, a), pbufs(c, a ^ 1), c->gid[p], c->gid[p ^ 1],
+  HIPCHK(launch_reorder(c->sp, c->perm, c->inv, pbufs(c, a), pbufs(c, a ^ 1), c->gid[p],
+                        c->gid[p ^ 1],
                         c->info[p], c->info[p ^ 1], c->xref, wslots(c, p), wslots(c, p ^ 1),
                         c->d_walls, move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
                         c->d_flags, s));
   HIPCHK(launch_search(c->grid, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
-                       nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
+                       c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
   c->pcur ^= 1;
   c->n_rebuilds += 1;
@@ -257,10 +271,14 @@ int collect_timing(dem_ctx* c) {
   return DEM_OK;
 }
 
+// Explicit Euler searches after the force evaluation of the same step, so the
+// stored forces move with the particles to stay readable by dem_get_forces.
+int move_forces_at_search(const dem_ctx* c) { return c->cfg.integrator == 1 ? 1 : 0; }
+
 int eager_rebuild(dem_ctx* c) {
   int rc = timed_begin(c, 1);
   if (rc) return rc;
-  rc = enqueue_rebuild(c, 1, 0);
+  rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
   if (rc) return rc;
   return timed_end(c);
 }
@@ -298,7 +316,7 @@ int get_chunk_graph(dem_ctx* c, hipGraphExec_t* out) {
     for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 0, j);
   } else {
     for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 2, j);
-    if (rc == DEM_OK) rc = enqueue_rebuild(c, 1, 0);
+    if (rc == DEM_OK) rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
   }
   if (rc == DEM_OK) {
     hipError_t e = launch_tick(c->d_clock, K, c->stream);
@@ -583,7 +601,7 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
   c->h = c->cfg.cell_factor * c->dmax * (1.0 + 1e-9);
   c->skin = c->rs - c->dmax;
   GridDev& g = c->grid;
-  int64_t nkeys = 64;
+  int total_bits = 0;
   for (int k = 0; k < 3; ++k) {
     g.lo[k] = c->cfg.domain_lo[k];
     g.hi[k] = c->cfg.domain_hi[k];
@@ -591,14 +609,38 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
     double cc = n > 0 ? ceil(span / c->h) : 1.0;
     if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
     g.nc[k] = std::max(1, (int)cc);
-    g.nb[k] = (g.nc[k] + 3) / 4;
-    nkeys *= g.nb[k];
+    int b = 0;
+    while ((1 << b) < g.nc[k]) ++b;
+    g.bits[k] = b;
+    total_bits += b;
   }
-  if (nkeys > ((int64_t)1 << 30))
-    return set_err(DEM_EINVAL, "cell grid of %lld cells is too large; shrink the domain box",
-                   (long long)nkeys);
+  if (total_bits > 30)
+    return set_err(DEM_EINVAL,
+                   "cell grid %dx%dx%d needs a 2^%d key space; shrink the domain box", g.nc[0],
+                   g.nc[1], g.nc[2], total_bits);
+  const int64_t nkeys = (int64_t)1 << total_bits;
   g.h = n > 0 ? c->h : 1.0;
   g.n_keys = nkeys;
+  // Morton tables: bit b of axis a goes to the next free key bit, taking
+  // levels b = 0, 1, ... and axes x, y, z in turn
+  std::vector<uint32_t> mort[3];
+  {
+    int pos_of[3][32];
+    int next = 0;
+    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
+    for (int b = 0; b < maxb; ++b)
+      for (int a = 0; a < 3; ++a)
+        if (b < g.bits[a]) pos_of[a][b] = next++;
+    for (int a = 0; a < 3; ++a) {
+      mort[a].resize((size_t)g.nc[a]);
+      for (int cidx = 0; cidx < g.nc[a]; ++cidx) {
+        uint32_t key = 0;
+        for (int b = 0; b < g.bits[a]; ++b)
+          if ((cidx >> b) & 1) key |= 1u << pos_of[a][b];
+        mort[a][(size_t)cidx] = key;
+      }
+    }
+  }
 
   // neighbour capacity: spheres of radius rmin whose centres lie within r_s of
   // a centre fit in a ball of radius r_s + rmin (packing density <= 0.7405),
@@ -650,12 +692,15 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
   rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((nkeys + 1 + 1023) / 1024 + 1));
   rc = rc ? rc : dalloc_t(c, &c->perm0, N);
   rc = rc ? rc : dalloc_t(c, &c->perm, N);
+  rc = rc ? rc : dalloc_t(c, &c->inv, N);
   rc = rc ? rc : dalloc_t(c, &c->d_pp, (size_t)kMaxTypes * kMaxTypes);
   rc = rc ? rc : dalloc_t(c, &c->d_pw, (size_t)kMaxTypes * kMaxTypes);
   rc = rc ? rc : dalloc_t(c, &c->d_walls, (size_t)kMaxWalls);
   rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
+  uint32_t* d_mort[3] = {nullptr, nullptr, nullptr};
+  for (int a = 0; a < 3; ++a) rc = rc ? rc : dalloc_t(c, &d_mort[a], mort[a].size());
   if (rc) {
     free_particles(c);
     return rc;
@@ -669,19 +714,15 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
     for (int b = 0; b < kMaxTypes; ++b) {
       if (!c->mat_set[a] || !c->mat_set[b]) continue;
       const dem_material &A = c->mat[a], &B = c->mat[b];
-      PairCoef& q = pp[a * kMaxTypes + b];
-      q.Ye = eff_youngs(A, B);
-      q.Ge = eff_shear(A, B);
-      double e = a == b ? A.restitution : 0.5 * (A.restitution + B.restitution);
-      q.ceta = damping_factor(e);
-      q.mu = a == b ? A.friction : 0.5 * (A.friction + B.friction);
-      q.mur = a == b ? A.rolling_friction : 0.5 * (A.rolling_friction + B.rolling_friction);
-      PairCoef& r = pw[a * kMaxTypes + b];  // particle type a against wall material b
-      r.Ye = q.Ye;
-      r.Ge = q.Ge;
-      r.ceta = damping_factor(B.restitution);
-      r.mu = B.friction;
-      r.mur = B.rolling_friction;
+      const double Ye = eff_youngs(A, B), Ge = eff_shear(A, B);
+      // unlike particle types: mean restitution, friction and rolling friction
+      const double e = a == b ? A.restitution : 0.5 * (A.restitution + B.restitution);
+      const double mu = a == b ? A.friction : 0.5 * (A.friction + B.friction);
+      const double mur =
+          a == b ? A.rolling_friction : 0.5 * (A.rolling_friction + B.rolling_friction);
+      pp[a * kMaxTypes + b] = make_coef(Ye, Ge, e, mu, mur);
+      // particle type a against wall material b: the wall's e, mu, mu_r
+      pw[a * kMaxTypes + b] = make_coef(Ye, Ge, B.restitution, B.friction, B.rolling_friction);
     }
 
   // packed particle state
@@ -693,15 +734,20 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
     const double m = c->mat[t].density * (4.0 / 3.0) * kPi * R * R * R;
     const double I = 0.4 * m * R * R;
     hpos[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], R);
-    hvel[i] = vel ? make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], m)
-                  : make_double4(0.0, 0.0, 0.0, m);
-    homg[i] = omega ? make_double4(omega[3 * i], omega[3 * i + 1], omega[3 * i + 2], I)
-                    : make_double4(0.0, 0.0, 0.0, I);
+    hvel[i] = vel ? make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 1.0 / m)
+                  : make_double4(0.0, 0.0, 0.0, 1.0 / m);
+    homg[i] = omega ? make_double4(omega[3 * i], omega[3 * i + 1], omega[3 * i + 2], 1.0 / I)
+                    : make_double4(0.0, 0.0, 0.0, 1.0 / I);
     hgid[i] = (int)i;
     hinfo[i] = t;
   }
   hipStream_t s = c->stream;
   if ((rc = wait_user(c))) return rc;
+  for (int a = 0; a < 3; ++a) {
+    HIPCHK(hipMemcpyAsync(d_mort[a], mort[a].data(), mort[a].size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s));
+    g.mort[a] = d_mort[a];
+  }
   HIPCHK(hipMemcpyAsync(c->d_pp, pp.data(), pp.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->d_pw, pw.data(), pw.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
   if (!c->walls.empty())
@@ -923,14 +969,16 @@ int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, 
   for (size_t p = 0; p < n; ++p) {
     for (int k = 0; k < rl[p]; ++k) {
       const int64_t e = nbr_entry((int)p, k, c->max_nb);
-      const int q = nb[(size_t)e];
+      const int jr = nb[(size_t)e];
+      const int q = jr & 0x7fffffff;  // bit 31: touching at the last evaluation
       if (h.gid[p] >= h.gid[q]) continue;
       Rec r;
       r.i = h.gid[p];
       r.j = h.gid[q];
-      r.d[0] = hs[(size_t)e];
-      r.d[1] = hs[(size_t)c->cap + (size_t)e];
-      r.d[2] = hs[2 * (size_t)c->cap + (size_t)e];
+      const bool has_hist = (jr & (int)0x80000000u) != 0;
+      r.d[0] = has_hist ? hs[(size_t)e] : 0.0;
+      r.d[1] = has_hist ? hs[(size_t)c->cap + (size_t)e] : 0.0;
+      r.d[2] = has_hist ? hs[2 * (size_t)c->cap + (size_t)e] : 0.0;
       const double dx = h.pos[q].x - h.pos[p].x, dy = h.pos[q].y - h.pos[p].y,
                    dz = h.pos[q].z - h.pos[p].z;
       const double rsum = h.pos[p].w + h.pos[q].w;

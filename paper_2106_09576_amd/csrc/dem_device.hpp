@@ -24,10 +24,13 @@ enum : int {
 };
 
 // Per material pair constants of the Hertz-Mindlin law (effective-parameter
-// table of Sec. 2.1): effective Young's and shear moduli, the damping factor
-// -2 sqrt(5/6) beta, friction and rolling friction of the pair.
+// table of Sec. 2.1), with Y_e, G_e the effective moduli and
+// beta = ln e / sqrt(ln^2 e + pi^2):  kn = 4/3 Y_e, kt = 8 G_e,
+// en = -2 sqrt(5/6) beta sqrt(2 Y_e), et = -2 sqrt(5/6) beta sqrt(8 G_e),
+// so that k_n = kn q, k_t = kt q, eta_n = en sqrt(m_e q), eta_t = et sqrt(m_e q)
+// with q = sqrt(R_e delta_n); mu and mur are the friction coefficients.
 struct PairCoef {
-  double Ye, Ge, ceta, mu, mur, pad0, pad1, pad2;
+  double kn, kt, en, et, mu, mur, pad0, pad1;
 };
 
 // Analytic wall.  kind 0: plane (point p, unit normal nrm into the domain,
@@ -43,14 +46,17 @@ struct WallDev {
   double t_on, t_off;
 };
 
-// Uniform cell grid: cell (cx,cy,cz) = floor((x - lo)/h); cells are ordered
-// in 4x4x4 bricks (Morton order inside a brick), one extra key for inactive
-// particles at the end.
+// Uniform cell grid: cell (cx,cy,cz) = floor((x - lo)/h).  Cells are ordered
+// along a Morton (Z-order) curve: key = mort[0][cx] | mort[1][cy] | mort[2][cz]
+// where mort[a] spreads the bits of a coordinate into its interleaved key
+// positions (axes with fewer bits drop out of the interleave at the top).
+// One extra key, n_keys, collects inactive particles.
 struct GridDev {
   double lo[3], hi[3], h;
   int nc[3];
-  int nb[3];
-  int64_t n_keys;  // 64 * nb0 * nb1 * nb2
+  int bits[3];
+  const uint32_t* mort[3];
+  int64_t n_keys;  // 2^(bits0 + bits1 + bits2)
 };
 
 struct StepParams {
@@ -66,7 +72,7 @@ struct StepParams {
 };
 
 // Particle arrays in sorted (spatial) order.  pos = (x, y, z, R),
-// vel = (v, m), omg = (omega, I).
+// vel = (v, 1/m), omg = (omega, 1/I).
 struct ParticleBufs {
   double4* pos;
   double4* vel;
@@ -74,7 +80,9 @@ struct ParticleBufs {
 };
 
 // Neighbour list, one row per particle in wave-slab column-major layout:
-// entry (i, k) lives at ((i / 64) * max_nb + k) * 64 + i % 64.
+// entry (i, k) lives at ((i / 64) * max_nb + k) * 64 + i % 64.  Bit 31 of a
+// neighbour index is set while the pair touches; the stored history of an
+// entry without bit 31 is undefined and stands for zero.
 struct NbrList {
   int* nbr;      // sorted index of the neighbour
   double* hist;  // 3 planes of tangential overlap (x, y, z), stride cap
@@ -106,15 +114,16 @@ hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const in
                           int* perm0, hipStream_t s);
 hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
                             const int* start, const int* gid, int* perm, hipStream_t s);
-hipError_t launch_reorder(const StepParams& sp, const int* perm, ParticleBufs src,
+// perm: new -> old index; inv receives old -> new
+hipError_t launch_reorder(const StepParams& sp, const int* perm, int* inv, ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, int* flags, hipStream_t s);
 hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
-                         const int* info, const int* start, const int* perm, NbrList old_l,
-                         NbrList new_l, int* flags, hipStream_t s);
+                         const int* info, const int* start, const int* perm, const int* inv,
+                         NbrList old_l, NbrList new_l, int* flags, hipStream_t s);
 
 // force + integration kernels.  mode: 0 = velocity Verlet fused (second half
 // kick of this step, first half kick and drift of the next), 1 = velocity

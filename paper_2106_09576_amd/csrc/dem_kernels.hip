@@ -47,19 +47,13 @@ __device__ inline bool finite3(double a, double b, double c) {
   return isfinite(a) && isfinite(b) && isfinite(c);
 }
 
-__device__ inline uint32_t spread2(uint32_t v) { return (v & 1u) | ((v & 2u) << 2); }
-
 __device__ inline int cell_coord(double x, double lo, double h, int nc) {
   int c = (int)floor((x - lo) / h);
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
 __device__ inline uint32_t cell_key(const GridDev& g, int cx, int cy, int cz) {
-  uint32_t brick = ((uint32_t)(cz >> 2) * (uint32_t)g.nb[1] + (uint32_t)(cy >> 2)) *
-                       (uint32_t)g.nb[0] +
-                   (uint32_t)(cx >> 2);
-  uint32_t in = spread2(cx & 3) | (spread2(cy & 3) << 1) | (spread2(cz & 3) << 2);
-  return brick * 64u + in;
+  return g.mort[0][cx] | g.mort[1][cy] | g.mort[2][cz];
 }
 
 // ------------------------------------------------------------------ fill
@@ -330,7 +324,8 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
 // Gather every particle array into sorted order, record the reference
 // position of the displacement guard, and redo the particle-wall search at
 // the new position carrying the tangential overlap of walls already listed.
-__global__ void k_reorder(StepParams sp, const int* __restrict__ perm, ParticleBufs src,
+__global__ void k_reorder(StepParams sp, const int* __restrict__ perm, int* __restrict__ inv,
+                          ParticleBufs src,
                           ParticleBufs dst, const int* __restrict__ gid_src,
                           int* __restrict__ gid_dst, const int* __restrict__ info_src,
                           int* __restrict__ info_dst, double4* __restrict__ xref,
@@ -342,6 +337,7 @@ __global__ void k_reorder(StepParams sp, const int* __restrict__ perm, ParticleB
   const int n = sp.n;
   if (p >= n) return;
   int o = perm[p];
+  inv[o] = p;
   double4 ps = src.pos[o];
   dst.pos[p] = ps;
   dst.vel[p] = src.vel[o];
@@ -386,14 +382,14 @@ __global__ void k_reorder(StepParams sp, const int* __restrict__ perm, ParticleB
   for (; c < kWallSlots; ++c) ws_dst.wid[(int64_t)c * n + p] = -1;
 }
 
-hipError_t launch_reorder(const StepParams& sp, const int* perm, ParticleBufs src,
+hipError_t launch_reorder(const StepParams& sp, const int* perm, int* inv, ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, int* flags, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, perm, src, dst,
+  hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, perm, inv, src, dst,
                      gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, F_src,
                      T_src, F_dst, T_dst, flags);
   return hipGetLastError();
@@ -402,14 +398,18 @@ hipError_t launch_reorder(const StepParams& sp, const int* perm, ParticleBufs sr
 // ------------------------------------------------------------------ search
 
 // Broad + fine search for particle p (sorted order): scan its own and the 26
-// surrounding cells, keep q != p with |x_q - x_p|^2 < r_s^2 (evaluated in a
-// fixed order without fused operations), and carry the
-// tangential overlap of pairs that were already listed: the old row of p is
-// found through the sort permutation (old index of p and q).
+// surrounding cells and keep q != p with |x_q - x_p|^2 < r_s^2 (evaluated in
+// a fixed order without fused operations).  Pairs that touch now go to the
+// front of the row and the others behind them, so that during the next K
+// steps the history accesses of a wavefront stay in few cache lines.  Then
+// the tangential overlaps are carried over: every entry of p's old row that
+// was touching (bit 31) names its partner by old index; inv maps it to the new
+// index, which is looked up in the new row.  Entries without bit 31 have zero
+// history, which is therefore never stored.
 __global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ pos,
                          const int* __restrict__ info, const int* __restrict__ start,
-                         const int* __restrict__ perm, NbrList old_l, NbrList new_l,
-                         int* __restrict__ flags) {
+                         const int* __restrict__ perm, const int* __restrict__ inv,
+                         NbrList old_l, NbrList new_l, int* __restrict__ flags) {
   int p = xcd_block() * kBlock + threadIdx.x;
   if (p >= sp.n) return;
   const int max_nb = sp.max_nb;
@@ -417,165 +417,256 @@ __global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ p
     new_l.rowlen[p] = 0;
     return;
   }
-  double4 pp = pos[p];
-  int cx = cell_coord(pp.x, g.lo[0], g.h, g.nc[0]);
-  int cy = cell_coord(pp.y, g.lo[1], g.h, g.nc[1]);
-  int cz = cell_coord(pp.z, g.lo[2], g.h, g.nc[2]);
-  const int op = perm[p];
-  const int olen = old_l.rowlen[op];
-  int cnt = 0;
+  const double4 pp = pos[p];
+  const int cx = cell_coord(pp.x, g.lo[0], g.h, g.nc[0]);
+  const int cy = cell_coord(pp.y, g.lo[1], g.h, g.nc[1]);
+  const int cz = cell_coord(pp.z, g.lo[2], g.h, g.nc[2]);
+  int front = 0;  // touching pairs fill slots 0, 1, ...
+  int back = 0;   // the others fill slots max_nb-1, max_nb-2, ...
   bool overflow = false;
   for (int dz = -1; dz <= 1; ++dz) {
-    int z = cz + dz;
+    const int z = cz + dz;
     if (z < 0 || z >= g.nc[2]) continue;
     for (int dy = -1; dy <= 1; ++dy) {
-      int y = cy + dy;
+      const int y = cy + dy;
       if (y < 0 || y >= g.nc[1]) continue;
+      const uint32_t kyz = g.mort[1][y] | g.mort[2][z];
       for (int dx = -1; dx <= 1; ++dx) {
-        int x = cx + dx;
+        const int x = cx + dx;
         if (x < 0 || x >= g.nc[0]) continue;
-        uint32_t key = cell_key(g, x, y, z);
-        int s = start[key], e = start[key + 1];
+        const uint32_t key = g.mort[0][x] | kyz;
+        const int s = start[key], e = start[key + 1];
         for (int q = s; q < e; ++q) {
           if (q == p) continue;
-          double4 pq = pos[q];
-          double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
-          double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
+          const double4 pq = pos[q];
+          const double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
+          const double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
           if (!(d2 < sp.rs2)) continue;
-          if (cnt == max_nb) {
+          if (front + back == max_nb) {
             overflow = true;
             continue;
           }
-          const int oq = perm[q];
-          double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-          for (int k = 0; k < olen; ++k) {
-            int64_t oe = nbr_entry(op, k, max_nb);
-            if (old_l.nbr[oe] == oq) {
-              h0 = old_l.hist[oe];
-              h1 = old_l.hist[old_l.cap + oe];
-              h2 = old_l.hist[2 * old_l.cap + oe];
-              break;
-            }
-          }
-          int64_t ne = nbr_entry(p, cnt, max_nb);
-          new_l.nbr[ne] = q;
-          new_l.hist[ne] = h0;
-          new_l.hist[new_l.cap + ne] = h1;
-          new_l.hist[2 * new_l.cap + ne] = h2;
-          ++cnt;
+          const double rsum = pp.w + pq.w;
+          const int slot = d2 < rsum * rsum ? front++ : max_nb - 1 - back++;
+          new_l.nbr[nbr_entry(p, slot, max_nb)] = q;
         }
       }
     }
   }
+  // close the gap: the non-touching entries follow the touching ones
+  for (int b = 0; b < back; ++b) {
+    const int64_t from = nbr_entry(p, max_nb - 1 - b, max_nb);
+    const int64_t to = nbr_entry(p, front + b, max_nb);
+    if (from != to) new_l.nbr[to] = new_l.nbr[from];
+  }
+  const int len = front + back;
+  new_l.rowlen[p] = len;
   if (overflow) atomicOr(flags, kFlagNbrOverflow);
-  new_l.rowlen[p] = cnt;
+  // history carry-over for pairs touching at the last force evaluation
+  const int op = perm[p];
+  const int olen = old_l.rowlen[op];
+  for (int k = 0; k < olen; ++k) {
+    const int64_t oe = nbr_entry(op, k, max_nb);
+    const int ojr = old_l.nbr[oe];
+    if (!(ojr & (int)0x80000000u)) continue;
+    const int q = inv[ojr & 0x7fffffff];
+    for (int m = 0; m < len; ++m) {
+      const int64_t ne = nbr_entry(p, m, max_nb);
+      if (new_l.nbr[ne] == q) {
+        new_l.nbr[ne] = q | (int)0x80000000u;
+        new_l.hist[ne] = old_l.hist[oe];
+        new_l.hist[new_l.cap + ne] = old_l.hist[old_l.cap + oe];
+        new_l.hist[2 * new_l.cap + ne] = old_l.hist[2 * old_l.cap + oe];
+        break;
+      }
+    }
+  }
 }
 
 hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
-                         const int* info, const int* start, const int* perm, NbrList old_l,
-                         NbrList new_l, int* flags, hipStream_t s) {
+                         const int* info, const int* start, const int* perm, const int* inv,
+                         NbrList old_l, NbrList new_l, int* flags, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_search, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, g, sp, pos, info,
-                     start, perm, old_l, new_l, flags);
+                     start, perm, inv, old_l, new_l, flags);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------- contact law
 
-// The Hertz-Mindlin law in arithmetic type R (double: plain FP64; float: the
-// constitutive part in FP32 with geometry, history and sums in FP64).
-// Inputs: overlap dn >= 0, unit normal n (from body i to body j), contact
-// relative velocity vij, wrel = omega_i - omega_j, effective mass and radius,
-// lever arm Ri, pair coefficients; the tangential overlap dtl (FP64) is
-// updated in place.  Output: force on i and torque on i.
+// Square roots and reciprocals.  Double: the hardware estimates refined by two
+// Newton-Raphson steps each (rsqrt: y <- y (3 - x y^2) / 2; reciprocal:
+// y <- y (2 - x y)), a few ulp from the correctly rounded value, far cheaper
+// than the correctly rounded library sequences.  Float: the single hardware
+// instructions (about 1 ulp).  Every function of a symmetric argument returns
+// the same value whichever side of the pair evaluates it.
 template <typename R>
-__device__ inline void hertz_mindlin(const PairCoef& c, int rolling, double dt, R dn,
-                                     const R n[3], const R vij[3], const R wrel[3], R me,
-                                     R Re, R Ri, double dtl[3], double Fi[3], double Mi[3]) {
-  R vn = (vij[0] * n[0] + vij[1] * n[1]) + vij[2] * n[2];
-  R vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
-  R vrt[3] = {vij[0] - vrn[0], vij[1] - vrn[1], vij[2] - vrn[2]};
-  // Eq. (delta_t): the history stays in FP64
-  for (int k = 0; k < 3; ++k) dtl[k] = dtl[k] + (double)vrt[k] * dt;
-  R dt3[3] = {(R)dtl[0], (R)dtl[1], (R)dtl[2]};
+struct Fast;
 
-  const R Ye = (R)c.Ye, Ge = (R)c.Ge, ceta = (R)c.ceta, mu = (R)c.mu;
-  R q = sqrt(Re * dn);
-  R kn = (R)(4.0 / 3.0) * Ye * q;
-  R kt = (R)8.0 * Ge * q;
-  R Sn = (R)2.0 * Ye * q;
-  R St = (R)8.0 * Ge * q;
-  R etan = ceta * sqrt(Sn * me);
-  R etat = ceta * sqrt(St * me);
-  R Fn[3], Ft[3];
-  for (int k = 0; k < 3; ++k) {
-    Fn[k] = -(kn * dn) * n[k] - etan * vrn[k];
-    Ft[k] = -(kt * dt3[k]) - etat * vrt[k];
+template <>
+struct Fast<double> {
+  static __device__ __forceinline__ double rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
   }
-  R fn = sqrt((Fn[0] * Fn[0] + Fn[1] * Fn[1]) + Fn[2] * Fn[2]);
-  R ft = sqrt((Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2]);
-  if (ft >= mu * fn && ft > (R)0) {
+  static __device__ __forceinline__ double rcp(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+  }
+  static __device__ __forceinline__ double sqrt(double x) {
+    return x > 0.0 ? x * rsqrt(x) : 0.0;
+  }
+};
+
+template <>
+struct Fast<float> {
+  static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+
+// The Hertz-Mindlin law (Sec. 2.1) in arithmetic type R for one contact, given
+// the overlap dn >= 0, the unit normal n from body i to body j, the contact
+// relative velocity vij, wrel = omega_i - omega_j, the effective mass and
+// radius and the lever arm Ri.  The tangential overlap dtl stays in FP64 and
+// is updated in place (Eq. delta_t before the force, Coulomb truncation of
+// Eqs. coulomb_overlap..3 after it).  Output: force and torque on body i.
+// With k_n = (4/3) Y_e q, k_t = 8 G_e q, eta = -2 sqrt(5/6) beta sqrt(S m_e),
+// q = sqrt(R_e dn), the per-pair constants are c.kn = 4/3 Y_e, c.kt = 8 G_e,
+// c.en = -2 sqrt(5/6) beta sqrt(2 Y_e), c.et = -2 sqrt(5/6) beta sqrt(8 G_e).
+template <typename R>
+__device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, double dt, R dn,
+                                       const R n[3], const R vij[3], const R wrel[3], R me,
+                                       R Re, R Ri, double dtl[3], double Fi[3], double Mi[3]) {
+  using M = Fast<R>;
+  const R vn = (vij[0] * n[0] + vij[1] * n[1]) + vij[2] * n[2];
+  const R vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
+  const R vrt[3] = {vij[0] - vrn[0], vij[1] - vrn[1], vij[2] - vrn[2]};
+  dtl[0] = dtl[0] + (double)vrt[0] * dt;
+  dtl[1] = dtl[1] + (double)vrt[1] * dt;
+  dtl[2] = dtl[2] + (double)vrt[2] * dt;
+  const R q = M::sqrt(Re * dn);
+  const R kn = (R)c.kn * q;
+  const R kt = (R)c.kt * q;
+  const R sq = M::sqrt(me * q);
+  const R etan = (R)c.en * sq;
+  const R etat = (R)c.et * sq;
+  const R knd = kn * dn;
+  R Fn[3], Ft[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    Fn[k] = -(knd * n[k]) - etan * vrn[k];
+    Ft[k] = -(kt * (R)dtl[k]) - etat * vrt[k];
+  }
+  const R fn2 = (Fn[0] * Fn[0] + Fn[1] * Fn[1]) + Fn[2] * Fn[2];
+  const R ft2 = (Ft[0] * Ft[0] + Ft[1] * Ft[1]) + Ft[2] * Ft[2];
+  const R fn = M::sqrt(fn2);
+  const R mufn = (R)c.mu * fn;
+  if (ft2 >= mufn * mufn && ft2 > (R)0) {
+    const R ratio = mufn * M::rsqrt(ft2);
+    const R mikt = -M::rcp(kt);
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      R fhat = mu * fn * Ft[k] / ft;
-      R ftilde = fhat + etat * vrt[k];
-      dtl[k] = (double)(ftilde / (-kt));
+      const R fhat = ratio * Ft[k];
+      dtl[k] = (double)((fhat + etat * vrt[k]) * mikt);
       Ft[k] = fhat;
     }
   }
-  R nx[3] = {n[1] * Ft[2] - n[2] * Ft[1], n[2] * Ft[0] - n[0] * Ft[2],
-             n[0] * Ft[1] - n[1] * Ft[0]};
   R Mr[3] = {(R)0, (R)0, (R)0};
   if (rolling == 1) {
-    R wn = sqrt((wrel[0] * wrel[0] + wrel[1] * wrel[1]) + wrel[2] * wrel[2]);
-    if (wn > (R)0) {
-      R mur = (R)c.mur;
-      for (int k = 0; k < 3; ++k) Mr[k] = -mur * Re * fn * (wrel[k] / wn);
+    const R wn2 = (wrel[0] * wrel[0] + wrel[1] * wrel[1]) + wrel[2] * wrel[2];
+    if (wn2 > (R)0) {
+      const R sc = -((R)c.mur * Re * fn) * M::rsqrt(wn2);
+      Mr[0] = sc * wrel[0];
+      Mr[1] = sc * wrel[1];
+      Mr[2] = sc * wrel[2];
     }
   }
+  const R nx[3] = {n[1] * Ft[2] - n[2] * Ft[1], n[2] * Ft[0] - n[0] * Ft[2],
+                   n[0] * Ft[1] - n[1] * Ft[0]};
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     Fi[k] = (double)(Fn[k] + Ft[k]);
     Mi[k] = (double)(Ri * nx[k] + Mr[k]);
   }
 }
 
-// Particle i against neighbour j, evaluated from i's side.  Returns the force
-// and torque on i; dtl is the history of the directed pair (i -> j).
+// Particle i against a touching neighbour j, evaluated from i's side
+// (pos = (x, R), vel = (v, 1/m), omg = (omega, 1/I)).  Written so that the
+// evaluation from j's side gives exactly -F and -delta_t: every symmetric
+// quantity is formed from commutative operations of the two particles' data.
 template <typename R>
-__device__ inline void pp_contact(const PairCoef& c, int rolling, double dt, double4 xi,
-                                  double4 vi, double4 wi, double4 xj, double4 vj, double4 wj,
-                                  double dtl[3], double Fi[3], double Mi[3]) {
-  double dx[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
-  double d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
-  double rsum = xi.w + xj.w;
-  if (!(d2 < rsum * rsum)) {
-    dtl[0] = dtl[1] = dtl[2] = 0.0;
-    Fi[0] = Fi[1] = Fi[2] = 0.0;
-    Mi[0] = Mi[1] = Mi[2] = 0.0;
-    return;
-  }
-  double d = sqrt(d2);
-  double dn = rsum - d;
-  if (dn < 0.0) dn = 0.0;
-  double nd[3] = {dx[0] / d, dx[1] / d, dx[2] / d};
+__device__ __forceinline__ void pp_contact(const PairCoef& c, int rolling, double dt,
+                                           double4 xi, double4 vi, double4 wi, double4 xj,
+                                           double4 vj, double4 wj, double dtl[3], double Fi[3],
+                                           double Mi[3]);
+
+template <>
+__device__ __forceinline__ void pp_contact<double>(const PairCoef& c, int rolling, double dt,
+                                                   double4 xi, double4 vi, double4 wi,
+                                                   double4 xj, double4 vj, double4 wj,
+                                                   double dtl[3], double Fi[3], double Mi[3]) {
+  using M = Fast<double>;
+  const double dx[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
+  const double d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
   const double Ri = xi.w, Rj = xj.w;
-  double rw[3] = {Ri * wi.x + Rj * wj.x, Ri * wi.y + Rj * wj.y, Ri * wi.z + Rj * wj.z};
-  double rwxn[3] = {rw[1] * nd[2] - rw[2] * nd[1], rw[2] * nd[0] - rw[0] * nd[2],
-                    rw[0] * nd[1] - rw[1] * nd[0]};
-  double vd[3] = {(vi.x - vj.x) + rwxn[0], (vi.y - vj.y) + rwxn[1], (vi.z - vj.z) + rwxn[2]};
-  double wd[3] = {wi.x - wj.x, wi.y - wj.y, wi.z - wj.z};
-  double me = 1.0 / (1.0 / vi.w + 1.0 / vj.w);
-  double Re = 1.0 / (1.0 / Ri + 1.0 / Rj);
-  R n[3] = {(R)nd[0], (R)nd[1], (R)nd[2]};
-  R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
-  R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
-  hertz_mindlin<R>(c, rolling, dt, (R)dn, n, vij, wrel, (R)me, (R)Re, (R)Ri, dtl, Fi, Mi);
+  const double rsum = Ri + Rj;
+  const double inv_d = M::rsqrt(d2);
+  double dn = rsum - d2 * inv_d;
+  if (dn < 0.0) dn = 0.0;
+  const double n[3] = {dx[0] * inv_d, dx[1] * inv_d, dx[2] * inv_d};
+  const double rw[3] = {Ri * wi.x + Rj * wj.x, Ri * wi.y + Rj * wj.y, Ri * wi.z + Rj * wj.z};
+  const double vij[3] = {(vi.x - vj.x) + (rw[1] * n[2] - rw[2] * n[1]),
+                         (vi.y - vj.y) + (rw[2] * n[0] - rw[0] * n[2]),
+                         (vi.z - vj.z) + (rw[0] * n[1] - rw[1] * n[0])};
+  const double wrel[3] = {wi.x - wj.x, wi.y - wj.y, wi.z - wj.z};
+  const double me = M::rcp(vi.w + vj.w);
+  const double Re = (Ri * Rj) * M::rcp(rsum);
+  hm_law<double>(c, rolling, dt, dn, n, vij, wrel, me, Re, Ri, dtl, Fi, Mi);
 }
 
+// FP32 contact law.  The overlap is formed without cancellation:
+// dn = (rsum^2 - d^2) / (rsum + d) with the numerator from FP64 positions.
+template <>
+__device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling, double dt,
+                                                  double4 xi, double4 vi, double4 wi,
+                                                  double4 xj, double4 vj, double4 wj,
+                                                  double dtl[3], double Fi[3], double Mi[3]) {
+  using M = Fast<float>;
+  const double dx[3] = {xj.x - xi.x, xj.y - xi.y, xj.z - xi.z};
+  const double d2 = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+  const double rsum = xi.w + xj.w;
+  const float d2f = (float)d2;
+  const float inv_d = M::rsqrt(d2f);
+  const float num = (float)(rsum * rsum - d2);
+  float dn = num * M::rcp((float)rsum + d2f * inv_d);
+  if (dn < 0.0f) dn = 0.0f;
+  const float n[3] = {(float)dx[0] * inv_d, (float)dx[1] * inv_d, (float)dx[2] * inv_d};
+  const float Ri = (float)xi.w, Rj = (float)xj.w;
+  const float rw[3] = {Ri * (float)wi.x + Rj * (float)wj.x, Ri * (float)wi.y + Rj * (float)wj.y,
+                       Ri * (float)wi.z + Rj * (float)wj.z};
+  const float vij[3] = {(float)(vi.x - vj.x) + (rw[1] * n[2] - rw[2] * n[1]),
+                        (float)(vi.y - vj.y) + (rw[2] * n[0] - rw[0] * n[2]),
+                        (float)(vi.z - vj.z) + (rw[0] * n[1] - rw[1] * n[0])};
+  const float wrel[3] = {(float)(wi.x - wj.x), (float)(wi.y - wj.y), (float)(wi.z - wj.z)};
+  const float me = M::rcp((float)(vi.w + vj.w));
+  const float Re = (Ri * Rj) * M::rcp(Ri + Rj);
+  hm_law<float>(c, rolling, dt, dn, n, vij, wrel, me, Re, Ri, dtl, Fi, Mi);
+}
+
+// Particle against wall W, the wall acting as a body of infinite mass and
+// radius whose contact point moves with the wall's surface velocity.
 template <typename R>
-__device__ inline void pw_contact(const PairCoef& c, int rolling, double dt, const WallDev& W,
-                                  double skin, double4 xi, double4 vi, double4 wi,
-                                  double dtl[3], double Fi[3], double Mi[3]) {
-  double x[3] = {xi.x, xi.y, xi.z};
+__device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, double dt,
+                                           const WallDev& W, double skin, double4 xi,
+                                           double4 vi, double4 wi, double dtl[3],
+                                           double Fi[3], double Mi[3]) {
+  const double x[3] = {xi.x, xi.y, xi.z};
   WallGeo g;
   wall_geo(W, x, xi.w, skin, true, g);
   if (!g.touching) {
@@ -584,24 +675,34 @@ __device__ inline void pw_contact(const PairCoef& c, int rolling, double dt, con
     Mi[0] = Mi[1] = Mi[2] = 0.0;
     return;
   }
-  double dn = g.dn < 0.0 ? 0.0 : g.dn;
-  double arm[3] = {g.xc[0] - W.ax[0], g.xc[1] - W.ax[1], g.xc[2] - W.ax[2]};
-  double vw[3] = {W.omega[1] * arm[2] - W.omega[2] * arm[1],
-                  W.omega[2] * arm[0] - W.omega[0] * arm[2],
-                  W.omega[0] * arm[1] - W.omega[1] * arm[0]};
+  const double dn = g.dn < 0.0 ? 0.0 : g.dn;
+  const double arm[3] = {g.xc[0] - W.ax[0], g.xc[1] - W.ax[1], g.xc[2] - W.ax[2]};
+  const double vw[3] = {W.omega[1] * arm[2] - W.omega[2] * arm[1],
+                        W.omega[2] * arm[0] - W.omega[0] * arm[2],
+                        W.omega[0] * arm[1] - W.omega[1] * arm[0]};
   const double Ri = xi.w;
-  double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
-  double rwxn[3] = {rw[1] * g.n[2] - rw[2] * g.n[1], rw[2] * g.n[0] - rw[0] * g.n[2],
-                    rw[0] * g.n[1] - rw[1] * g.n[0]};
-  double vd[3] = {(vi.x - vw[0]) + rwxn[0], (vi.y - vw[1]) + rwxn[1], (vi.z - vw[2]) + rwxn[2]};
-  double wd[3] = {wi.x - W.omega[0], wi.y - W.omega[1], wi.z - W.omega[2]};
-  R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
-  R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
-  R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
-  hertz_mindlin<R>(c, rolling, dt, (R)dn, n, vij, wrel, (R)vi.w, (R)Ri, (R)Ri, dtl, Fi, Mi);
+  const double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
+  const double vd[3] = {(vi.x - vw[0]) + (rw[1] * g.n[2] - rw[2] * g.n[1]),
+                        (vi.y - vw[1]) + (rw[2] * g.n[0] - rw[0] * g.n[2]),
+                        (vi.z - vw[2]) + (rw[0] * g.n[1] - rw[1] * g.n[0])};
+  const double wd[3] = {wi.x - W.omega[0], wi.y - W.omega[1], wi.z - W.omega[2]};
+  const R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
+  const R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
+  const R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
+  const R me = Fast<R>::rcp((R)vi.w);
+  hm_law<R>(c, rolling, dt, (R)dn, n, vij, wrel, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
 }
 
 // ------------------------------------------------------------------- force
+//
+// One thread per particle walks its row in order (every load of a row entry
+// is one coalesced access for the wavefront); the neighbour's velocities and
+// the pair history are loaded only when the pair touches.  Bit 31 of a row
+// entry marks "touching at the last evaluation" (history may be non-zero);
+// histories of other entries are zero and are neither read nor written.
+
+constexpr int kTouchedBit = (int)0x80000000u;
+constexpr int kIndexMask = 0x7fffffff;
 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kBlock)
@@ -634,25 +735,44 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
   double T[3] = {0.0, 0.0, 0.0};
   const int len = l.rowlen[i];
   const int max_nb = sp.max_nb;
+  const int64_t cap = l.cap;
   for (int k = 0; k < len; ++k) {
     const int64_t e = nbr_entry(i, k, max_nb);
-    const int j = l.nbr[e];
-    double4 xj = in.pos[j];
-    double4 vj = in.vel[j];
-    double4 wj = in.omg[j];
-    const int tj = info[j] & kTypeMask;
-    double dtl[3] = {l.hist[e], l.hist[l.cap + e], l.hist[2 * l.cap + e]};
-    double Fi[3], Mi[3];
-    pp_contact<R>(ppc[ti * kMaxTypes + tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
-    l.hist[e] = dtl[0];
-    l.hist[l.cap + e] = dtl[1];
-    l.hist[2 * l.cap + e] = dtl[2];
-    F[0] += Fi[0];
-    F[1] += Fi[1];
-    F[2] += Fi[2];
-    T[0] += Mi[0];
-    T[1] += Mi[1];
-    T[2] += Mi[2];
+    const int jr = l.nbr[e];
+    const int j = jr & kIndexMask;
+    const double4 xj = in.pos[j];
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double rsum = xi.w + xj.w;
+    if (d2 < rsum * rsum) {
+      const double4 vj = in.vel[j];
+      const double4 wj = in.omg[j];
+      const int tj = info[j] & kTypeMask;
+      double dtl[3] = {0.0, 0.0, 0.0};
+      if (jr & kTouchedBit) {
+        dtl[0] = l.hist[e];
+        dtl[1] = l.hist[cap + e];
+        dtl[2] = l.hist[2 * cap + e];
+      }
+      double Fi[3], Mi[3];
+      pp_contact<R>(ppc[ti * kMaxTypes + tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi,
+                    Mi);
+      l.hist[e] = dtl[0];
+      l.hist[cap + e] = dtl[1];
+      l.hist[2 * cap + e] = dtl[2];
+      if (!(jr & kTouchedBit)) l.nbr[e] = j | kTouchedBit;
+      F[0] += Fi[0];
+      F[1] += Fi[1];
+      F[2] += Fi[2];
+      T[0] += Mi[0];
+      T[1] += Mi[1];
+      T[2] += Mi[2];
+    } else if (jr & kTouchedBit) {
+      l.hist[e] = 0.0;
+      l.hist[cap + e] = 0.0;
+      l.hist[2 * cap + e] = 0.0;
+      l.nbr[e] = j;
+    }
   }
   // walls: time of this force evaluation
   const double t = (double)(*clock + step_rel) * dt;
@@ -681,10 +801,10 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
     T[1] += Mi[1];
     T[2] += Mi[2];
   }
-  // integration of particle i
-  const double m = vi.w, I = wi.w;
-  double a[3] = {F[0] / m + sp.g[0], F[1] / m + sp.g[1], F[2] / m + sp.g[2]};
-  double al[3] = {T[0] / I, T[1] / I, T[2] / I};
+  // integration of particle i (vel.w = 1/m, omg.w = 1/I)
+  const double im = vi.w, iI = wi.w;
+  const double a[3] = {F[0] * im + sp.g[0], F[1] * im + sp.g[1], F[2] * im + sp.g[2]};
+  const double al[3] = {T[0] * iI, T[1] * iI, T[2] * iI};
   if (MODE == 2) {
     // explicit Euler, Eq. (integ_EE): x with the old velocity
     xi.x = xi.x + vi.x * dt;
@@ -760,13 +880,14 @@ __global__ void k_kick_drift(StepParams sp, ParticleBufs st, const int* __restri
   double4 x = st.pos[i], v = st.vel[i], w = st.omg[i];
   double4 f = F[i], tq = T[i];
   const double h = sp.hdt, dt = sp.dt;
-  double a0 = f.x / v.w + sp.g[0], a1 = f.y / v.w + sp.g[1], a2 = f.z / v.w + sp.g[2];
+  // vel.w = 1/m, omg.w = 1/I
+  double a0 = f.x * v.w + sp.g[0], a1 = f.y * v.w + sp.g[1], a2 = f.z * v.w + sp.g[2];
   v.x = v.x + a0 * h;
   v.y = v.y + a1 * h;
   v.z = v.z + a2 * h;
-  w.x = w.x + (tq.x / w.w) * h;
-  w.y = w.y + (tq.y / w.w) * h;
-  w.z = w.z + (tq.z / w.w) * h;
+  w.x = w.x + (tq.x * w.w) * h;
+  w.y = w.y + (tq.y * w.w) * h;
+  w.z = w.z + (tq.z * w.w) * h;
   x.x = x.x + v.x * dt;
   x.y = x.y + v.y * dt;
   x.z = x.z + v.z * dt;
@@ -804,7 +925,7 @@ __global__ void k_stats(StepParams sp, const double4* __restrict__ pos,
     int len = l.rowlen[i];
     e = (unsigned long long)len;
     for (int k = 0; k < len; ++k) {
-      int j = l.nbr[nbr_entry(i, k, sp.max_nb)];
+      int j = l.nbr[nbr_entry(i, k, sp.max_nb)] & 0x7fffffff;
       double4 xj = pos[j];
       double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
       double d2 = (dx * dx + dy * dy) + dz * dz;
