@@ -27,6 +27,11 @@
  *   - call order: dem_create -> dem_set_material -> dem_add_*_wall ->
  *     dem_set_particles -> dem_step / dem_get_*.  Calling dem_set_particles
  *     again restarts the simulation (time 0, all contact history cleared).
+ *   - a context holds n_instances >= 1 independent simulations ("instances")
+ *     that share dt, gravity, domain box, search settings and precision and
+ *     advance together: one dem_step launches each kernel once for all of
+ *     them.  Materials, walls and particles are per instance; particle and
+ *     wall ids are local to their instance.
  */
 #ifndef DEM_H
 #define DEM_H
@@ -74,7 +79,7 @@ typedef struct {
   int32_t precision;         /* 0 plain FP64; 1 contact law in FP32 with
                                 positions, velocities, tangential history and
                                 force sums in FP64 */
-  int32_t n_instances;       /* must be 1 */
+  int32_t n_instances;       /* independent simulations in the batch, 1..2048 */
   int32_t max_neighbors;     /* candidate neighbours kept per particle;
                                 0 = derived from r_s and the smallest radius */
   void* hip_stream;          /* optional hipStream_t the library orders its
@@ -83,7 +88,7 @@ typedef struct {
 } dem_config;
 
 typedef struct {
-  int64_t n_particles;     /* particles given to dem_set_particles          */
+  int64_t n_particles;     /* particles of all instances                    */
   int64_t n_active;        /* not deactivated by leaving the domain box     */
   int64_t n_list_entries;  /* directed candidate entries (2 per pair)       */
   int64_t n_touching;      /* directed entries whose spheres overlap        */
@@ -92,7 +97,7 @@ typedef struct {
   int64_t n_rebuilds;      /* contact searches run, including the first     */
   int32_t max_neighbors;   /* capacity per particle in use                  */
   int32_t precision;
-  double r_s, cell_size, skin, d_max;
+  double r_s, cell_size, skin, d_max;  /* of instance 0 */
   int64_t n_cells;         /* cell keys of the grid (Morton-padded)          */
   int64_t device_bytes;    /* device memory held by the context             */
 } dem_stats;
@@ -100,15 +105,15 @@ typedef struct {
 /* Create a context on the current HIP device.  cfg is copied.  Fails with
    DEM_EINVAL for dt <= 0, an empty domain, rebuild_interval < 1, threshold or
    cell_factor < 1, an unknown integrator/rolling model/precision or
-   n_instances != 1; DEM_ENODEV if the device is not gfx950. */
+   n_instances outside [1, 2048]; DEM_ENODEV if the device is not gfx950. */
 int dem_create(const dem_config* cfg, dem_ctx** out_ctx);
 /* Release every device buffer of the context.  NULL is ignored. */
 void dem_destroy(dem_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
 const char* dem_last_error(dem_ctx* ctx);
 
-/* Material of particle type / wall material id `type` (0 <= type < 16).
-   instance must be 0. */
+/* Material of particle type / wall material id `type` (0 <= type < 16) of
+   instance `instance` (0 <= instance < n_instances). */
 int dem_set_material(dem_ctx* ctx, int32_t instance, int32_t type, const dem_material* m);
 
 /* Planar wall through `point` with unit `normal` pointing into the domain
@@ -138,23 +143,38 @@ int dem_add_cylinder_wall(dem_ctx* ctx, int32_t instance, const double axis_poin
                           int32_t inside, int32_t material, double omega, double t_on,
                           double t_off, int32_t* wall_id);
 
-/* Set n >= 0 particles (instance 0): positions (n x 3), velocities and
+/* Set n >= 0 particles of one instance: positions (n x 3), velocities and
    angular velocities (n x 3, NULL = zero), radii (n, > 0) and material types
    (n, NULL = type 0; each type's material must be set).  Masses are
-   rho (4/3) pi R^3 and moments of inertia (2/5) m R^2.  Allocates the
-   device state, runs the first contact search at these positions with all
-   tangential overlaps zero, and sets the stored forces to zero (the first
-   velocity-Verlet half kick sees gravity only).  DEM_ECAPACITY if a particle
-   already has more neighbours than max_neighbors. */
+   rho (4/3) pi R^3 and moments of inertia (2/5) m R^2.  The inputs are
+   copied; the batch is built on the device (first contact search at these
+   positions with all tangential overlaps zero, stored forces zero so the
+   first velocity-Verlet half kick sees gravity only) immediately when
+   n_instances == 1, otherwise by dem_commit or the first dem_step/dem_get_*
+   once every instance has particles.  Setting particles again restarts the
+   whole batch from the inputs last given for each instance.  DEM_ECAPACITY
+   (from the call that builds the batch) if a particle already has more
+   neighbours than max_neighbors. */
 int dem_set_particles(dem_ctx* ctx, int32_t instance, int64_t n, const double* pos,
                       const double* vel, const double* omega, const double* radius,
                       const int32_t* type);
-/* Same with device pointers (caller-owned, read on the library's stream). */
+/* Same with device pointers (caller-owned, read on the library's stream and
+   staged through host memory for validation). */
 int dem_set_particles_device(dem_ctx* ctx, int32_t instance, int64_t n, const double* pos,
                              const double* vel, const double* omega, const double* radius,
                              const int32_t* type);
 
-/* Advance n_steps >= 0 steps.  Synchronous: returns after the work finished.
+/* Domain box of one instance, replacing the config's domain_lo/domain_hi for
+   it (cell grid and deactivation box).  Called before dem_set_particles for
+   that instance. */
+int dem_set_instance_domain(dem_ctx* ctx, int32_t instance, const double lo[3],
+                            const double hi[3]);
+
+/* Build the batch on the device now (all instances must have particles).
+   Returns the errors described for dem_set_particles. */
+int dem_commit(dem_ctx* ctx);
+
+/* Advance every instance by n_steps >= 0 steps.  Synchronous: returns after the work finished.
    Contact searches run at every step number that is a multiple of
    rebuild_interval.  Errors (DEM_EUNSTABLE, DEM_ECAPACITY) are sticky: the
    state is frozen at the step where they were detected and later dem_step

@@ -1,10 +1,13 @@
 // Host runtime of the MI355X DEM library: the C ABI declared in include/dem.h.
 //
-// A context owns all device buffers of one simulation, one HIP stream (default
-// priority) and up to four instantiated HIP graphs, one per parity of the
-// ping-pong buffers, each holding one K-step chunk: the contact search
-// (Sec. 3.2, every K steps as in the "constant" detection of Sec. 3.1) followed
-// by K force+integration launches and a clock tick.
+// A context owns all device buffers of a batch of independent simulations
+// ("instances", one or more), one HIP stream (default priority) and up to four
+// instantiated HIP graphs, one per parity of the ping-pong buffers, each
+// holding one K-step chunk: the contact search (Sec. 3.2, every K steps as in
+// the "constant" detection of Sec. 3.1) followed by K force+integration
+// launches and a clock tick.  The particles of all instances live in one
+// array (each tagged with its instance), so every kernel launch covers the
+// whole batch and uneven instance sizes need no load balancing.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,25 +41,43 @@ int set_err(int code, const char* fmt, ...) {
 
 }  // namespace
 
+// Host-side description of one instance: materials, walls, the particles
+// given to dem_set_particles (kept until the batch is built on the device)
+// and the search geometry derived from them.
+struct Instance {
+  dem_material mat[kMaxTypes]{};
+  bool mat_set[kMaxTypes]{};
+  std::vector<WallDev> walls;
+  bool staged = false;
+  bool own_domain = false;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int64_t n = 0;
+  std::vector<double> pos, vel, omg, rad;
+  std::vector<int32_t> type;
+  // derived when the batch is built
+  double dmax = 0, rs = 0, h = 0, skin = 0;
+  int64_t p_begin = 0;
+  int w_begin = 0;
+  GridDev grid{};
+  uint32_t key_base = 0;
+};
+
 struct dem_ctx {
   dem_config cfg{};
   int device = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev_user = nullptr;
-  dem_material mat[kMaxTypes]{};
-  bool mat_set[kMaxTypes]{};
-  std::vector<WallDev> walls;
+  std::vector<Instance> inst;
 
-  // particle state
+  // particle state of the whole batch
   int n = 0;
   bool ready = false;
   bool failed = false;
   int fail_code = 0;
   int max_nb = 0;
   int64_t cap = 0;
-  GridDev grid{};
   StepParams sp{};
-  double dmax = 0, rs = 0, h = 0, skin = 0;
+  int64_t n_keys = 0;
 
   std::vector<void*> allocs;
   size_t dev_bytes = 0;
@@ -74,6 +95,7 @@ struct dem_ctx {
   int *perm0 = nullptr, *perm = nullptr, *inv = nullptr;
   PairCoef *d_pp = nullptr, *d_pw = nullptr;
   WallDev* d_walls = nullptr;
+  InstDev* d_inst = nullptr;
   int* d_flags = nullptr;
   int64_t* d_clock = nullptr;
   unsigned long long* d_stats = nullptr;
@@ -138,8 +160,9 @@ void free_particles(dem_ctx* c) {
   c->n = 0;
 }
 
-int check_instance(int32_t instance) {
-  if (instance != 0) return set_err(DEM_EINVAL, "instance %d: only instance 0 exists", instance);
+int check_instance(const dem_ctx* c, int32_t instance) {
+  if (instance < 0 || instance >= (int32_t)c->inst.size())
+    return set_err(DEM_EINVAL, "instance %d out of [0, %d)", instance, (int)c->inst.size());
   return DEM_OK;
 }
 
@@ -202,20 +225,21 @@ WallSlots wslots(dem_ctx* c, int k) { return WallSlots{c->wid[k], c->whist[k]}; 
 int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
   hipStream_t s = c->stream;
   const int a = c->cur, p = c->pcur;
-  HIPCHK(launch_fill_i32(c->count, 0, c->grid.n_keys + 1, s));
-  HIPCHK(launch_keys(c->grid, c->sp, c->pos[a], c->vel[a], c->info[p], c->xref, check_guard,
+  HIPCHK(launch_fill_i32(c->count, 0, c->n_keys + 1, s));
+  HIPCHK(launch_keys(c->d_inst, c->sp, c->pos[a], c->vel[a], c->info[p], c->xref, check_guard,
                      c->keys, c->rank, c->count, c->d_flags, s));
-  HIPCHK(launch_scan(c->count, c->start, c->grid.n_keys + 1, c->tile_sums, s));
+  HIPCHK(launch_scan(c->count, c->start, c->n_keys + 1, c->tile_sums, s));
   HIPCHK(launch_scatter(c->n, c->keys, c->rank, c->start, c->perm0, s));
-  HIPCHK(launch_cell_rank(c->n, c->grid.n_keys, c->perm0, c->keys, c->start, c->gid[p],
+  HIPCHK(launch_cell_rank(c->n, c->n_keys, c->perm0, c->keys, c->start, c->gid[p],
                           c->perm, s));
-  HIPCHK(launch_reorder(c->sp, c->perm, c->inv, pbufs(c, a), pbufs(c, a ^ 1), c->gid[p],
+  HIPCHK(launch_reorder(c->sp, c->d_inst, c->perm, c->inv, pbufs(c, a), pbufs(c, a ^ 1),
+                        c->gid[p],
                         c->gid[p ^ 1],
                         c->info[p], c->info[p ^ 1], c->xref, wslots(c, p), wslots(c, p ^ 1),
                         c->d_walls, move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
                         c->d_flags, s));
-  HIPCHK(launch_search(c->grid, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
+  HIPCHK(launch_search(c->d_inst, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
                        c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
   c->pcur ^= 1;
@@ -225,7 +249,8 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
 
 int enqueue_force(dem_ctx* c, int mode, int64_t step_rel) {
   const int a = c->cur, p = c->pcur;
-  HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_pp, c->d_pw, c->d_walls, pbufs(c, a),
+  HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_inst, c->d_pp, c->d_pw, c->d_walls,
+                      pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
                       c->d_clock, step_rel, c->d_flags, c->stream));
   c->cur ^= 1;
@@ -377,9 +402,9 @@ int flags_to_error(dem_ctx* c, int flags) {
   if (flags & kFlagNonFinite)
     return set_err(DEM_EUNSTABLE, "non-finite particle state (flags 0x%x)", flags);
   return set_err(DEM_EUNSTABLE,
-                 "a particle moved more than half the skin (%.3g m) between two contact "
+                 "a particle moved more than half the skin between two contact "
                  "searches; lower rebuild_interval or dt (flags 0x%x)",
-                 c->skin, flags);
+                 flags);
 }
 
 // host copy of the current particle arrays in sorted order
@@ -415,10 +440,254 @@ int snapshot(dem_ctx* c, HostSnapshot& h, bool want_pos, bool want_vel, bool wan
   return DEM_OK;
 }
 
+int commit(dem_ctx* c);
+
+// The batch is built on the device at the first call that needs it.
 int require_ready(dem_ctx* c) {
   if (!c) return set_err(DEM_EINVAL, "null context");
-  if (!c->ready) return set_err(DEM_ESTATE, "particles not set (call dem_set_particles)");
+  if (!c->ready) {
+    for (const Instance& I : c->inst)
+      if (!I.staged) return set_err(DEM_ESTATE, "particles not set (call dem_set_particles)");
+    if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
+    return commit(c);
+  }
   return DEM_OK;
+}
+
+// Build the whole batch on the device from the staged instances: search
+// geometry per instance, one key range per instance grid, concatenated walls
+// and material-pair tables, packed particle state, then the first contact
+// search at the initial positions with all histories zero.
+int commit(dem_ctx* c) {
+  free_particles(c);
+  const int B = (int)c->inst.size();
+  int64_t N = 0;
+  for (const Instance& I : c->inst) N += I.n;
+  if (N > ((int64_t)1 << 30)) return set_err(DEM_EINVAL, "too many particles in the batch");
+  const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
+  int64_t total_keys = 0;
+  double bound_nb = 16.0;
+  size_t mort_total = 0;
+  int n_walls = 0;
+  for (int b = 0; b < B; ++b) {
+    Instance& I = c->inst[(size_t)b];
+    double rmin = INFINITY, rmax = 0.0;
+    for (double r : I.rad) {
+      rmin = std::min(rmin, r);
+      rmax = std::max(rmax, r);
+    }
+    // search geometry: r_s = min(threshold, cell_factor) d_max, h >= r_s
+    I.dmax = 2.0 * rmax;
+    I.rs = f * I.dmax;
+    I.h = c->cfg.cell_factor * I.dmax * (1.0 + 1e-9);
+    I.skin = I.rs - I.dmax;
+    GridDev& g = I.grid;
+    int bits_total = 0;
+    for (int k = 0; k < 3; ++k) {
+      g.lo[k] = I.own_domain ? I.lo[k] : c->cfg.domain_lo[k];
+      g.hi[k] = I.own_domain ? I.hi[k] : c->cfg.domain_hi[k];
+      const double span = g.hi[k] - g.lo[k];
+      const double cc = I.n > 0 ? ceil(span / I.h) : 1.0;
+      if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
+      g.nc[k] = std::max(1, (int)cc);
+      int bb = 0;
+      while ((1 << bb) < g.nc[k]) ++bb;
+      g.bits[k] = bb;
+      bits_total += bb;
+      mort_total += (size_t)g.nc[k];
+    }
+    if (bits_total > 30)
+      return set_err(DEM_EINVAL, "instance %d: cell grid %dx%dx%d is too large; shrink the domain",
+                     b, g.nc[0], g.nc[1], g.nc[2]);
+    g.h = I.n > 0 ? I.h : 1.0;
+    g.n_keys = (int64_t)1 << bits_total;
+    I.key_base = (uint32_t)total_keys;
+    total_keys += g.n_keys;
+    if (total_keys >= ((int64_t)1 << 30))
+      return set_err(DEM_EINVAL, "the cell grids of the batch need more than 2^30 cells");
+    if (I.n > 0) {
+      // spheres of radius rmin whose centres lie within r_s of a centre fit in a
+      // ball of radius r_s + rmin (packing density <= 0.7405), 25% margin
+      const double ratio = (I.rs + rmin) / rmin;
+      bound_nb = std::max(bound_nb, 0.7405 * ratio * ratio * ratio * 1.25);
+    }
+    I.w_begin = n_walls;
+    n_walls += (int)I.walls.size();
+  }
+  int max_nb = c->cfg.max_neighbors;
+  if (max_nb == 0) max_nb = (int)std::min(512.0, ceil(bound_nb));
+  c->max_nb = max_nb;
+  c->n = (int)N;
+  c->n_keys = total_keys;
+  const int64_t npad = ((N + 63) / 64) * 64;
+  c->cap = npad * max_nb;
+
+  StepParams& sp = c->sp;
+  sp.dt = c->cfg.dt;
+  sp.hdt = 0.5 * c->cfg.dt;
+  for (int k = 0; k < 3; ++k) sp.g[k] = c->cfg.gravity[k];
+  sp.n = (int)N;
+  sp.max_nb = max_nb;
+  sp.rolling = c->cfg.rolling_model;
+  sp.n_keys = (uint32_t)total_keys;
+
+  // allocations
+  const size_t NN = (size_t)std::max<int64_t>(N, 1);
+  int rc = DEM_OK;
+  for (int b = 0; b < 2 && rc == DEM_OK; ++b) {
+    rc = rc ? rc : dalloc_t(c, &c->pos[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->vel[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->omg[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->gid[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->info[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->F[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->T[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->wid[b], NN * kWallSlots);
+    rc = rc ? rc : dalloc_t(c, &c->whist[b], NN * kWallSlots * 3);
+    rc = rc ? rc : dalloc_t(c, &c->nbr[b], (size_t)std::max<int64_t>(c->cap, 1));
+    rc = rc ? rc : dalloc_t(c, &c->hist[b], (size_t)std::max<int64_t>(c->cap, 1) * 3);
+    rc = rc ? rc : dalloc_t(c, &c->rowlen[b], NN);
+  }
+  rc = rc ? rc : dalloc_t(c, &c->xref, NN);
+  rc = rc ? rc : dalloc_t(c, &c->keys, NN);
+  rc = rc ? rc : dalloc_t(c, &c->rank, NN);
+  rc = rc ? rc : dalloc_t(c, &c->count, (size_t)total_keys + 1);
+  rc = rc ? rc : dalloc_t(c, &c->start, (size_t)total_keys + 2);
+  rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((total_keys + 1 + 1023) / 1024 + 1));
+  rc = rc ? rc : dalloc_t(c, &c->perm0, NN);
+  rc = rc ? rc : dalloc_t(c, &c->perm, NN);
+  rc = rc ? rc : dalloc_t(c, &c->inv, NN);
+  rc = rc ? rc : dalloc_t(c, &c->d_pp, (size_t)B * kMaxTypes * kMaxTypes);
+  rc = rc ? rc : dalloc_t(c, &c->d_pw, (size_t)B * kMaxTypes * kMaxTypes);
+  rc = rc ? rc : dalloc_t(c, &c->d_walls, (size_t)std::max(n_walls, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_inst, (size_t)B);
+  rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
+  rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
+  rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
+  uint32_t* d_mort = nullptr;
+  rc = rc ? rc : dalloc_t(c, &d_mort, std::max<size_t>(mort_total, 1));
+  if (rc) {
+    free_particles(c);
+    return rc;
+  }
+
+  // Morton tables (bit b of axis a goes to the next free key bit, taking
+  // levels b = 0, 1, ... and axes x, y, z in turn), instance table, walls and
+  // material-pair tables
+  std::vector<uint32_t> hmort;
+  hmort.reserve(mort_total);
+  std::vector<InstDev> hinst((size_t)B);
+  std::vector<WallDev> hwalls;
+  std::vector<PairCoef> pp((size_t)B * kMaxTypes * kMaxTypes), pw(pp.size());
+  memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
+  memset(pw.data(), 0, pw.size() * sizeof(PairCoef));
+  for (int b = 0; b < B; ++b) {
+    Instance& I = c->inst[(size_t)b];
+    GridDev& g = I.grid;
+    int pos_of[3][32];
+    int next = 0;
+    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
+    for (int lvl = 0; lvl < maxb; ++lvl)
+      for (int a = 0; a < 3; ++a)
+        if (lvl < g.bits[a]) pos_of[a][lvl] = next++;
+    for (int a = 0; a < 3; ++a) {
+      g.mort[a] = d_mort + hmort.size();
+      for (int ci = 0; ci < g.nc[a]; ++ci) {
+        uint32_t key = 0;
+        for (int lvl = 0; lvl < g.bits[a]; ++lvl)
+          if ((ci >> lvl) & 1) key |= 1u << pos_of[a][lvl];
+        hmort.push_back(key);
+      }
+    }
+    InstDev& D = hinst[(size_t)b];
+    D.grid = g;
+    D.key_base = I.key_base;
+    D.wall_begin = I.w_begin;
+    D.wall_end = I.w_begin + (int)I.walls.size();
+    D.coef_base = b * kMaxTypes * kMaxTypes;
+    D.rs2 = I.rs * I.rs;
+    D.guard2 = (0.5 * I.skin) * (0.5 * I.skin);
+    D.skin = I.skin;
+    hwalls.insert(hwalls.end(), I.walls.begin(), I.walls.end());
+    for (int ta = 0; ta < kMaxTypes; ++ta)
+      for (int tb = 0; tb < kMaxTypes; ++tb) {
+        if (!I.mat_set[ta] || !I.mat_set[tb]) continue;
+        const dem_material &A = I.mat[ta], &M = I.mat[tb];
+        const double Ye = eff_youngs(A, M), Ge = eff_shear(A, M);
+        // unlike particle types: mean restitution, friction and rolling friction
+        const double e = ta == tb ? A.restitution : 0.5 * (A.restitution + M.restitution);
+        const double mu = ta == tb ? A.friction : 0.5 * (A.friction + M.friction);
+        const double mur =
+            ta == tb ? A.rolling_friction : 0.5 * (A.rolling_friction + M.rolling_friction);
+        const size_t idx = (size_t)D.coef_base + (size_t)ta * kMaxTypes + (size_t)tb;
+        pp[idx] = make_coef(Ye, Ge, e, mu, mur);
+        // particle type ta against wall material tb: the wall's e, mu, mu_r
+        pw[idx] = make_coef(Ye, Ge, M.restitution, M.friction, M.rolling_friction);
+      }
+  }
+
+  // packed particle state (1/m and 1/I are stored: the law needs 1/m_i + 1/m_j)
+  std::vector<double4> hpos(NN), hvel(NN), homg(NN);
+  std::vector<int> hgid(NN), hinfo(NN);
+  int64_t q = 0;
+  for (int b = 0; b < B; ++b) {
+    Instance& I = c->inst[(size_t)b];
+    I.p_begin = q;
+    const bool hv = !I.vel.empty(), hw = !I.omg.empty(), ht = !I.type.empty();
+    for (int64_t i = 0; i < I.n; ++i, ++q) {
+      const int t = ht ? I.type[(size_t)i] : 0;
+      const double R = I.rad[(size_t)i];
+      const double m = I.mat[t].density * (4.0 / 3.0) * kPi * R * R * R;
+      const double Iner = 0.4 * m * R * R;
+      const double* x = &I.pos[3 * (size_t)i];
+      hpos[(size_t)q] = make_double4(x[0], x[1], x[2], R);
+      hvel[(size_t)q] = hv ? make_double4(I.vel[3 * i], I.vel[3 * i + 1], I.vel[3 * i + 2], 1.0 / m)
+                           : make_double4(0.0, 0.0, 0.0, 1.0 / m);
+      homg[(size_t)q] = hw ? make_double4(I.omg[3 * i], I.omg[3 * i + 1], I.omg[3 * i + 2], 1.0 / Iner)
+                           : make_double4(0.0, 0.0, 0.0, 1.0 / Iner);
+      hgid[(size_t)q] = (int)q;
+      hinfo[(size_t)q] = t | (b << kInstShift);
+    }
+  }
+  hipStream_t s = c->stream;
+  if ((rc = wait_user(c))) return rc;
+  if (!hmort.empty())
+    HIPCHK(hipMemcpyAsync(d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_pp, pp.data(), pp.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->d_pw, pw.data(), pw.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
+  if (!hwalls.empty())
+    HIPCHK(hipMemcpyAsync(c->d_walls, hwalls.data(), hwalls.size() * sizeof(WallDev),
+                          hipMemcpyHostToDevice, s));
+  c->cur = 0;
+  c->pcur = 0;
+  if (N > 0) {
+    HIPCHK(hipMemcpyAsync(c->pos[0], hpos.data(), N * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->vel[0], hvel.data(), N * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->omg[0], homg.data(), N * sizeof(double4), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->gid[0], hgid.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->info[0], hinfo.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  // zero-filled: forces of both parities, empty old list and wall slots
+  HIPCHK(launch_fill_i32((int*)c->F[0], 0, (int64_t)NN * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->T[0], 0, (int64_t)NN * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->F[1], 0, (int64_t)NN * 8, s));
+  HIPCHK(launch_fill_i32((int*)c->T[1], 0, (int64_t)NN * 8, s));
+  HIPCHK(launch_fill_i32(c->rowlen[0], 0, (int64_t)NN, s));
+  HIPCHK(launch_fill_i32(c->wid[0], -1, (int64_t)NN * kWallSlots, s));
+  HIPCHK(launch_fill_i32(c->d_flags, 0, 1, s));
+  HIPCHK(launch_fill_i32((int*)c->d_clock, 0, 2, s));
+  HIPCHK(launch_fill_i32((int*)c->xref, 0, (int64_t)NN * 8, s));
+  c->step = 0;
+  c->host_base = 0;
+  c->n_rebuilds = 0;
+  if ((rc = enqueue_rebuild(c, 0, 0))) return rc;
+  int flags = 0;
+  if ((rc = read_flags(c, &flags))) return rc;
+  c->ready = true;
+  return flags_to_error(c, flags);
 }
 
 }  // namespace
@@ -448,7 +717,8 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
     return set_err(DEM_EINVAL, "rolling_model must be 0 or 1");
   if (cfg->precision < 0 || cfg->precision > 1)
     return set_err(DEM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 law)");
-  if (cfg->n_instances != 1) return set_err(DEM_EINVAL, "n_instances must be 1");
+  if (cfg->n_instances < 1 || cfg->n_instances > kMaxInstances)
+    return set_err(DEM_EINVAL, "n_instances must be in [1, %d]", kMaxInstances);
   if (cfg->max_neighbors < 0 || cfg->max_neighbors > 4096)
     return set_err(DEM_EINVAL, "max_neighbors out of range");
   int dev = 0;
@@ -463,6 +733,7 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
   dem_ctx* c = new dem_ctx();
   c->cfg = *cfg;
   c->device = dev;
+  c->inst.resize((size_t)cfg->n_instances);
   e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_user, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -484,15 +755,16 @@ void dem_destroy(dem_ctx* c) {
 
 int dem_set_material(dem_ctx* c, int32_t instance, int32_t type, const dem_material* m) {
   if (!c || !m) return set_err(DEM_EINVAL, "null argument");
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (type < 0 || type >= kMaxTypes) return set_err(DEM_EINVAL, "type %d out of [0, 16)", type);
   if (!(m->density > 0.0) || !(m->youngs > 0.0) || !(m->poisson > -1.0 && m->poisson < 0.5) ||
       !(m->restitution > 0.0 && m->restitution <= 1.0) || !(m->friction >= 0.0) ||
       !(m->rolling_friction >= 0.0))
     return set_err(DEM_EINVAL, "invalid material values for type %d", type);
-  if (c->ready) return set_err(DEM_ESTATE, "materials are set before dem_set_particles");
-  c->mat[type] = *m;
-  c->mat_set[type] = true;
+  Instance& I = c->inst[(size_t)instance];
+  if (I.staged) return set_err(DEM_ESTATE, "materials are set before dem_set_particles");
+  I.mat[type] = *m;
+  I.mat_set[type] = true;
   return DEM_OK;
 }
 
@@ -501,11 +773,12 @@ int dem_add_planar_wall(dem_ctx* c, int32_t instance, const double point[3],
                         const double axis_point[3], const double omega[3], double t_on,
                         double t_off, int32_t* wall_id) {
   if (!c || !point || !normal) return set_err(DEM_EINVAL, "null argument");
-  if (int rc = check_instance(instance)) return rc;
-  if ((int)c->walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
-  if (material < 0 || material >= kMaxTypes || !c->mat_set[material])
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if ((int)I.walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !I.mat_set[material])
     return set_err(DEM_EINVAL, "wall material %d not set", material);
-  if (c->ready) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  if (I.staged) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
   WallDev W;
   memset(&W, 0, sizeof(W));
   W.kind = 0;
@@ -530,8 +803,8 @@ int dem_add_planar_wall(dem_ctx* c, int32_t instance, const double point[3],
   W.material = material;
   W.t_on = t_on;
   W.t_off = t_off;
-  if (wall_id) *wall_id = (int32_t)c->walls.size();
-  c->walls.push_back(W);
+  if (wall_id) *wall_id = (int32_t)I.walls.size();
+  I.walls.push_back(W);
   return DEM_OK;
 }
 
@@ -540,13 +813,14 @@ int dem_add_cylinder_wall(dem_ctx* c, int32_t instance, const double axis_point[
                           int32_t inside, int32_t material, double omega, double t_on,
                           double t_off, int32_t* wall_id) {
   if (!c || !axis_point || !axis_dir) return set_err(DEM_EINVAL, "null argument");
-  if (int rc = check_instance(instance)) return rc;
-  if ((int)c->walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
-  if (material < 0 || material >= kMaxTypes || !c->mat_set[material])
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if ((int)I.walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !I.mat_set[material])
     return set_err(DEM_EINVAL, "wall material %d not set", material);
   if (!(radius > 0.0) || !(s_max >= s_min))
     return set_err(DEM_EINVAL, "cylinder needs radius > 0 and s_max >= s_min");
-  if (c->ready) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  if (I.staged) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
   WallDev W;
   memset(&W, 0, sizeof(W));
   W.kind = 1;
@@ -563,8 +837,8 @@ int dem_add_cylinder_wall(dem_ctx* c, int32_t instance, const double axis_point[
   W.material = material;
   W.t_on = t_on;
   W.t_off = t_off;
-  if (wall_id) *wall_id = (int32_t)c->walls.size();
-  c->walls.push_back(W);
+  if (wall_id) *wall_id = (int32_t)I.walls.size();
+  I.walls.push_back(W);
   return DEM_OK;
 }
 
@@ -572,214 +846,57 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
                       const double* vel, const double* omega, const double* radius,
                       const int32_t* type) {
   if (!c) return set_err(DEM_EINVAL, "null context");
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (n < 0 || n > (int64_t)1 << 30) return set_err(DEM_EINVAL, "n out of range");
   if (n > 0 && (!pos || !radius)) return set_err(DEM_EINVAL, "pos and radius are required");
-  double rmin = INFINITY, rmax = 0.0;
+  Instance& I = c->inst[(size_t)instance];
   for (int64_t i = 0; i < n; ++i) {
     if (!(radius[i] > 0.0) || !std::isfinite(radius[i]))
       return set_err(DEM_EINVAL, "radius[%lld] must be > 0", (long long)i);
     int t = type ? type[i] : 0;
-    if (t < 0 || t >= kMaxTypes || !c->mat_set[t])
+    if (t < 0 || t >= kMaxTypes || !I.mat_set[t])
       return set_err(DEM_EINVAL, "particle %lld has type %d without material", (long long)i, t);
     for (int k = 0; k < 3; ++k)
       if (!std::isfinite(pos[3 * i + k]) || (vel && !std::isfinite(vel[3 * i + k])) ||
           (omega && !std::isfinite(omega[3 * i + k])))
         return set_err(DEM_EINVAL, "non-finite state of particle %lld", (long long)i);
-    rmin = std::min(rmin, radius[i]);
-    rmax = std::max(rmax, radius[i]);
   }
+  // setting particles again restarts the batch from the staged inputs
   free_particles(c);
   c->failed = false;
   c->fail_code = 0;
-  c->n = (int)n;
+  I.n = n;
+  I.pos.assign(pos, pos + 3 * n);
+  I.rad.assign(radius, radius + n);
+  I.vel.assign(vel ? vel : pos, vel ? vel + 3 * n : pos);
+  I.omg.assign(omega ? omega : pos, omega ? omega + 3 * n : pos);
+  I.type.assign(type ? type : (const int32_t*)nullptr, type ? type + n : (const int32_t*)nullptr);
+  I.staged = true;
+  if (c->inst.size() == 1) return commit(c);
+  return DEM_OK;
+}
 
-  // search geometry: r_s = min(threshold, cell_factor) d_max, h >= r_s
-  c->dmax = 2.0 * rmax;
-  const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
-  c->rs = f * c->dmax;
-  c->h = c->cfg.cell_factor * c->dmax * (1.0 + 1e-9);
-  c->skin = c->rs - c->dmax;
-  GridDev& g = c->grid;
-  int total_bits = 0;
+int dem_set_instance_domain(dem_ctx* c, int32_t instance, const double lo[3],
+                            const double hi[3]) {
+  if (!c || !lo || !hi) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if (I.staged) return set_err(DEM_ESTATE, "the domain is set before dem_set_particles");
+  for (int k = 0; k < 3; ++k)
+    if (!(hi[k] > lo[k]) || !std::isfinite(lo[k]) || !std::isfinite(hi[k]))
+      return set_err(DEM_EINVAL, "empty domain along axis %d", k);
   for (int k = 0; k < 3; ++k) {
-    g.lo[k] = c->cfg.domain_lo[k];
-    g.hi[k] = c->cfg.domain_hi[k];
-    double span = g.hi[k] - g.lo[k];
-    double cc = n > 0 ? ceil(span / c->h) : 1.0;
-    if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
-    g.nc[k] = std::max(1, (int)cc);
-    int b = 0;
-    while ((1 << b) < g.nc[k]) ++b;
-    g.bits[k] = b;
-    total_bits += b;
+    I.lo[k] = lo[k];
+    I.hi[k] = hi[k];
   }
-  if (total_bits > 30)
-    return set_err(DEM_EINVAL,
-                   "cell grid %dx%dx%d needs a 2^%d key space; shrink the domain box", g.nc[0],
-                   g.nc[1], g.nc[2], total_bits);
-  const int64_t nkeys = (int64_t)1 << total_bits;
-  g.h = n > 0 ? c->h : 1.0;
-  g.n_keys = nkeys;
-  // Morton tables: bit b of axis a goes to the next free key bit, taking
-  // levels b = 0, 1, ... and axes x, y, z in turn
-  std::vector<uint32_t> mort[3];
-  {
-    int pos_of[3][32];
-    int next = 0;
-    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
-    for (int b = 0; b < maxb; ++b)
-      for (int a = 0; a < 3; ++a)
-        if (b < g.bits[a]) pos_of[a][b] = next++;
-    for (int a = 0; a < 3; ++a) {
-      mort[a].resize((size_t)g.nc[a]);
-      for (int cidx = 0; cidx < g.nc[a]; ++cidx) {
-        uint32_t key = 0;
-        for (int b = 0; b < g.bits[a]; ++b)
-          if ((cidx >> b) & 1) key |= 1u << pos_of[a][b];
-        mort[a][(size_t)cidx] = key;
-      }
-    }
-  }
+  I.own_domain = true;
+  return DEM_OK;
+}
 
-  // neighbour capacity: spheres of radius rmin whose centres lie within r_s of
-  // a centre fit in a ball of radius r_s + rmin (packing density <= 0.7405),
-  // with 25% margin for overlaps
-  int max_nb = c->cfg.max_neighbors;
-  if (max_nb == 0) {
-    double ratio = n > 0 ? (c->rs + rmin) / rmin : 2.0;
-    double bound = 0.7405 * ratio * ratio * ratio * 1.25;
-    max_nb = (int)std::min(512.0, std::max(16.0, ceil(bound)));
-  }
-  c->max_nb = max_nb;
-  const int64_t npad = ((n + 63) / 64) * 64;
-  c->cap = npad * max_nb;
-
-  StepParams& sp = c->sp;
-  sp.dt = c->cfg.dt;
-  sp.hdt = 0.5 * c->cfg.dt;
-  for (int k = 0; k < 3; ++k) sp.g[k] = c->cfg.gravity[k];
-  sp.rs2 = c->rs * c->rs;
-  sp.guard2 = (0.5 * c->skin) * (0.5 * c->skin);
-  sp.skin = c->skin;
-  sp.n = (int)n;
-  sp.max_nb = max_nb;
-  sp.n_walls = (int)c->walls.size();
-  sp.rolling = c->cfg.rolling_model;
-
-  // allocations
-  const size_t N = (size_t)std::max<int64_t>(n, 1);
-  int rc = DEM_OK;
-  for (int b = 0; b < 2 && rc == DEM_OK; ++b) {
-    rc = rc ? rc : dalloc_t(c, &c->pos[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->vel[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->omg[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->gid[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->info[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->F[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->T[b], N);
-    rc = rc ? rc : dalloc_t(c, &c->wid[b], N * kWallSlots);
-    rc = rc ? rc : dalloc_t(c, &c->whist[b], N * kWallSlots * 3);
-    rc = rc ? rc : dalloc_t(c, &c->nbr[b], (size_t)std::max<int64_t>(c->cap, 1));
-    rc = rc ? rc : dalloc_t(c, &c->hist[b], (size_t)std::max<int64_t>(c->cap, 1) * 3);
-    rc = rc ? rc : dalloc_t(c, &c->rowlen[b], N);
-  }
-  rc = rc ? rc : dalloc_t(c, &c->xref, N);
-  rc = rc ? rc : dalloc_t(c, &c->keys, N);
-  rc = rc ? rc : dalloc_t(c, &c->rank, N);
-  rc = rc ? rc : dalloc_t(c, &c->count, (size_t)nkeys + 1);
-  rc = rc ? rc : dalloc_t(c, &c->start, (size_t)nkeys + 2);
-  rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((nkeys + 1 + 1023) / 1024 + 1));
-  rc = rc ? rc : dalloc_t(c, &c->perm0, N);
-  rc = rc ? rc : dalloc_t(c, &c->perm, N);
-  rc = rc ? rc : dalloc_t(c, &c->inv, N);
-  rc = rc ? rc : dalloc_t(c, &c->d_pp, (size_t)kMaxTypes * kMaxTypes);
-  rc = rc ? rc : dalloc_t(c, &c->d_pw, (size_t)kMaxTypes * kMaxTypes);
-  rc = rc ? rc : dalloc_t(c, &c->d_walls, (size_t)kMaxWalls);
-  rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
-  rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
-  rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
-  uint32_t* d_mort[3] = {nullptr, nullptr, nullptr};
-  for (int a = 0; a < 3; ++a) rc = rc ? rc : dalloc_t(c, &d_mort[a], mort[a].size());
-  if (rc) {
-    free_particles(c);
-    return rc;
-  }
-
-  // material-pair tables
-  std::vector<PairCoef> pp(kMaxTypes * kMaxTypes), pw(kMaxTypes * kMaxTypes);
-  memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
-  memset(pw.data(), 0, pw.size() * sizeof(PairCoef));
-  for (int a = 0; a < kMaxTypes; ++a)
-    for (int b = 0; b < kMaxTypes; ++b) {
-      if (!c->mat_set[a] || !c->mat_set[b]) continue;
-      const dem_material &A = c->mat[a], &B = c->mat[b];
-      const double Ye = eff_youngs(A, B), Ge = eff_shear(A, B);
-      // unlike particle types: mean restitution, friction and rolling friction
-      const double e = a == b ? A.restitution : 0.5 * (A.restitution + B.restitution);
-      const double mu = a == b ? A.friction : 0.5 * (A.friction + B.friction);
-      const double mur =
-          a == b ? A.rolling_friction : 0.5 * (A.rolling_friction + B.rolling_friction);
-      pp[a * kMaxTypes + b] = make_coef(Ye, Ge, e, mu, mur);
-      // particle type a against wall material b: the wall's e, mu, mu_r
-      pw[a * kMaxTypes + b] = make_coef(Ye, Ge, B.restitution, B.friction, B.rolling_friction);
-    }
-
-  // packed particle state
-  std::vector<double4> hpos(N), hvel(N), homg(N);
-  std::vector<int> hgid(N), hinfo(N);
-  for (int64_t i = 0; i < n; ++i) {
-    const int t = type ? type[i] : 0;
-    const double R = radius[i];
-    const double m = c->mat[t].density * (4.0 / 3.0) * kPi * R * R * R;
-    const double I = 0.4 * m * R * R;
-    hpos[i] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], R);
-    hvel[i] = vel ? make_double4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 1.0 / m)
-                  : make_double4(0.0, 0.0, 0.0, 1.0 / m);
-    homg[i] = omega ? make_double4(omega[3 * i], omega[3 * i + 1], omega[3 * i + 2], 1.0 / I)
-                    : make_double4(0.0, 0.0, 0.0, 1.0 / I);
-    hgid[i] = (int)i;
-    hinfo[i] = t;
-  }
-  hipStream_t s = c->stream;
-  if ((rc = wait_user(c))) return rc;
-  for (int a = 0; a < 3; ++a) {
-    HIPCHK(hipMemcpyAsync(d_mort[a], mort[a].data(), mort[a].size() * sizeof(uint32_t),
-                          hipMemcpyHostToDevice, s));
-    g.mort[a] = d_mort[a];
-  }
-  HIPCHK(hipMemcpyAsync(c->d_pp, pp.data(), pp.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(c->d_pw, pw.data(), pw.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));
-  if (!c->walls.empty())
-    HIPCHK(hipMemcpyAsync(c->d_walls, c->walls.data(), c->walls.size() * sizeof(WallDev),
-                          hipMemcpyHostToDevice, s));
-  c->cur = 0;
-  c->pcur = 0;
-  if (n > 0) {
-    HIPCHK(hipMemcpyAsync(c->pos[0], hpos.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->vel[0], hvel.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->omg[0], homg.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->gid[0], hgid.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(c->info[0], hinfo.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
-  }
-  // zero-filled: forces of both parities, empty old list and wall slots
-  HIPCHK(launch_fill_i32((int*)c->F[0], 0, (int64_t)N * 8, s));
-  HIPCHK(launch_fill_i32((int*)c->T[0], 0, (int64_t)N * 8, s));
-  HIPCHK(launch_fill_i32((int*)c->F[1], 0, (int64_t)N * 8, s));
-  HIPCHK(launch_fill_i32((int*)c->T[1], 0, (int64_t)N * 8, s));
-  HIPCHK(launch_fill_i32(c->rowlen[0], 0, (int64_t)N, s));
-  HIPCHK(launch_fill_i32(c->wid[0], -1, (int64_t)N * kWallSlots, s));
-  HIPCHK(launch_fill_i32(c->d_flags, 0, 1, s));
-  HIPCHK(launch_fill_i32((int*)c->d_clock, 0, 2, s));
-  HIPCHK(launch_fill_i32((int*)c->xref, 0, (int64_t)N * 8, s));
-  c->step = 0;
-  c->host_base = 0;
-  c->n_rebuilds = 0;
-  if ((rc = enqueue_rebuild(c, 0, 0))) return rc;
-  int flags = 0;
-  if ((rc = read_flags(c, &flags))) return rc;
-  c->ready = true;
-  return flags_to_error(c, flags);
+int dem_commit(dem_ctx* c) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  if (c->ready) return DEM_OK;
+  return require_ready(c);
 }
 
 int dem_set_particles_device(dem_ctx* c, int32_t instance, int64_t n, const double* pos,
@@ -865,12 +982,14 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
 int dem_get_state(dem_ctx* c, int32_t instance, double* pos, double* vel, double* omega,
                   uint8_t* active, double* time_out) {
   if (int rc = require_ready(c)) return rc;
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (int rc = wait_user(c)) return rc;
   HostSnapshot h;
   if (int rc = snapshot(c, h, pos != nullptr, vel != nullptr, omega != nullptr)) return rc;
+  const int64_t base = c->inst[(size_t)instance].p_begin;
   for (int p = 0; p < c->n; ++p) {
-    const int g = h.gid[p];
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    const int64_t g = h.gid[p] - base;
     if (pos) {
       pos[3 * g] = h.pos[p].x;
       pos[3 * g + 1] = h.pos[p].y;
@@ -895,8 +1014,8 @@ int dem_get_state(dem_ctx* c, int32_t instance, double* pos, double* vel, double
 int dem_get_state_device(dem_ctx* c, int32_t instance, double* pos, double* vel, double* omega,
                          uint8_t* active) {
   if (int rc = require_ready(c)) return rc;
-  if (int rc = check_instance(instance)) return rc;
-  const size_t n = (size_t)c->n;
+  if (int rc = check_instance(c, instance)) return rc;
+  const size_t n = (size_t)c->inst[(size_t)instance].n;
   std::vector<double> p(pos ? 3 * n : 0), v(vel ? 3 * n : 0), w(omega ? 3 * n : 0);
   std::vector<uint8_t> a(active ? n : 0);
   int rc = dem_get_state(c, instance, pos ? p.data() : nullptr, vel ? v.data() : nullptr,
@@ -911,7 +1030,7 @@ int dem_get_state_device(dem_ctx* c, int32_t instance, double* pos, double* vel,
 
 int dem_get_forces(dem_ctx* c, int32_t instance, double* force, double* torque) {
   if (int rc = require_ready(c)) return rc;
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (int rc = wait_user(c)) return rc;
   HostSnapshot h;
   if (int rc = snapshot(c, h, false, false, false)) return rc;
@@ -924,8 +1043,10 @@ int dem_get_forces(dem_ctx* c, int32_t instance, double* force, double* torque) 
                           c->stream));
   }
   if (int rc = finish(c)) return rc;
+  const int64_t base = c->inst[(size_t)instance].p_begin;
   for (size_t p = 0; p < n; ++p) {
-    const int g = h.gid[p];
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    const int64_t g = h.gid[p] - base;
     if (force) {
       force[3 * g] = F[p].x;
       force[3 * g + 1] = F[p].y;
@@ -943,7 +1064,7 @@ int dem_get_forces(dem_ctx* c, int32_t instance, double* force, double* torque) 
 int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, double* delta_t,
                      uint8_t* touching, int64_t* n_out) {
   if (int rc = require_ready(c)) return rc;
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
   if (int rc = wait_user(c)) return rc;
   HostSnapshot h;
@@ -966,15 +1087,17 @@ int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, 
     uint8_t t;
   };
   std::vector<Rec> out;
+  const int64_t base = c->inst[(size_t)instance].p_begin;
   for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
     for (int k = 0; k < rl[p]; ++k) {
       const int64_t e = nbr_entry((int)p, k, c->max_nb);
       const int jr = nb[(size_t)e];
       const int q = jr & 0x7fffffff;  // bit 31: touching at the last evaluation
       if (h.gid[p] >= h.gid[q]) continue;
       Rec r;
-      r.i = h.gid[p];
-      r.j = h.gid[q];
+      r.i = h.gid[p] - base;
+      r.j = h.gid[q] - base;
       const bool has_hist = (jr & (int)0x80000000u) != 0;
       r.d[0] = has_hist ? hs[(size_t)e] : 0.0;
       r.d[1] = has_hist ? hs[(size_t)c->cap + (size_t)e] : 0.0;
@@ -1005,7 +1128,7 @@ int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, 
 int dem_get_wall_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
                           double* delta_t, int64_t* n_out) {
   if (int rc = require_ready(c)) return rc;
-  if (int rc = check_instance(instance)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
   if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
   if (int rc = wait_user(c)) return rc;
   HostSnapshot h;
@@ -1025,16 +1148,19 @@ int dem_get_wall_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pa
     double d[3];
   };
   std::vector<Rec> out;
-  for (size_t p = 0; p < n; ++p)
+  const Instance& In = c->inst[(size_t)instance];
+  for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
     for (int s = 0; s < kWallSlots; ++s) {
       const int wi = w[(size_t)s * n + p];
       if (wi < 0) break;
       Rec r;
-      r.i = h.gid[p];
-      r.w = wi;
+      r.i = h.gid[p] - In.p_begin;
+      r.w = wi - In.w_begin;
       for (int k = 0; k < 3; ++k) r.d[k] = wh[(size_t)(3 * s + k) * n + p];
       out.push_back(r);
     }
+  }
   std::sort(out.begin(), out.end(),
             [](const Rec& a, const Rec& b) { return a.i != b.i ? a.i < b.i : a.w < b.w; });
   if (n_out) *n_out = (int64_t)out.size();
@@ -1083,11 +1209,12 @@ int dem_get_stats(dem_ctx* c, dem_stats* out) {
   out->n_rebuilds = c->n_rebuilds;
   out->max_neighbors = c->max_nb;
   out->precision = c->cfg.precision;
-  out->r_s = c->rs;
-  out->cell_size = c->h;
-  out->skin = c->skin;
-  out->d_max = c->dmax;
-  out->n_cells = c->grid.n_keys;
+  const Instance& I0 = c->inst[0];
+  out->r_s = I0.rs;
+  out->cell_size = I0.h;
+  out->skin = I0.skin;
+  out->d_max = I0.dmax;
+  out->n_cells = c->n_keys;
   out->device_bytes = (int64_t)c->dev_bytes;
   return DEM_OK;
 }

@@ -14,6 +14,8 @@ constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr int kTypeMask = 0xffff;
 constexpr int kInactive = 1 << 16;  // flag bit in the per-particle info word
+constexpr int kInstShift = 20;      // info bits 20..30: instance of the particle
+constexpr int kMaxInstances = 2048;
 
 // Sticky error bits raised by kernels (read once per dem_step call).
 enum : int {
@@ -46,11 +48,11 @@ struct WallDev {
   double t_on, t_off;
 };
 
-// Uniform cell grid: cell (cx,cy,cz) = floor((x - lo)/h).  Cells are ordered
-// along a Morton (Z-order) curve: key = mort[0][cx] | mort[1][cy] | mort[2][cz]
-// where mort[a] spreads the bits of a coordinate into its interleaved key
-// positions (axes with fewer bits drop out of the interleave at the top).
-// One extra key, n_keys, collects inactive particles.
+// Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).
+// Cells are ordered along a Morton (Z-order) curve:
+// key = mort[0][cx] | mort[1][cy] | mort[2][cz], where mort[a] spreads the
+// bits of a coordinate into its interleaved key positions (axes with fewer
+// bits drop out of the interleave at the top).
 struct GridDev {
   double lo[3], hi[3], h;
   int nc[3];
@@ -59,16 +61,26 @@ struct GridDev {
   int64_t n_keys;  // 2^(bits0 + bits1 + bits2)
 };
 
+// One independent simulation of a batch.  Its cells use the global keys
+// [key_base, key_base + grid.n_keys); its walls are walls[wall_begin,
+// wall_end); its material-pair constants start at coef_base in the tables.
+struct InstDev {
+  GridDev grid;
+  uint32_t key_base;
+  int wall_begin, wall_end;
+  int coef_base;
+  double rs2;     // squared search radius
+  double guard2;  // (skin/2)^2
+  double skin;    // r_s - d_max
+};
+
 struct StepParams {
   double dt, hdt;
   double g[3];
-  double rs2;      // squared search radius
-  double guard2;   // (skin/2)^2
-  double skin;
-  int n;           // number of particles (active + inactive)
+  int n;           // number of particles of all instances (active + inactive)
   int max_nb;      // neighbour slots per particle
-  int n_walls;
   int rolling;     // 0 none, 1 constant torque
+  uint32_t n_keys; // total cell keys; key n_keys collects inactive particles
 };
 
 // Particle arrays in sorted (spatial) order.  pos = (x, y, z, R),
@@ -104,7 +116,7 @@ __host__ __device__ inline int64_t nbr_entry(int i, int k, int max_nb) {
 // Every launcher enqueues on `s` and returns the hipError_t of the launch.
 
 hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
-hipError_t launch_keys(const GridDev& g, const StepParams& sp, const double4* pos,
+hipError_t launch_keys(const InstDev* inst, const StepParams& sp, const double4* pos,
                        const double4* vel, int* info, const double4* xref, int check_guard,
                        uint32_t* keys, int* rank, int* count, int* flags, hipStream_t s);
 // exclusive scan of count[0..m) into start[0..m], start[m] = total
@@ -115,13 +127,14 @@ hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const in
 hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
                             const int* start, const int* gid, int* perm, hipStream_t s);
 // perm: new -> old index; inv receives old -> new
-hipError_t launch_reorder(const StepParams& sp, const int* perm, int* inv, ParticleBufs src,
+hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
+                          ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, int* flags, hipStream_t s);
-hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
+hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double4* pos,
                          const int* info, const int* start, const int* perm, const int* inv,
                          NbrList old_l, NbrList new_l, int* flags, hipStream_t s);
 
@@ -129,7 +142,8 @@ hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* 
 // kick of this step, first half kick and drift of the next), 1 = velocity
 // Verlet last step of a call (second half kick, forces stored), 2 = explicit
 // Euler (forces at the current state, then the update; forces stored).
-hipError_t launch_force(int mode, int precision, const StepParams& sp, const PairCoef* pp,
+hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
+                        const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,

@@ -77,7 +77,8 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s) {
 // Cell key of every particle; deactivates particles outside the domain box,
 // checks the displacement guard and non-finite states, counts per cell (the
 // returned atomic slot is the particle's provisional rank in its cell).
-__global__ void k_keys(GridDev g, StepParams sp, const double4* __restrict__ pos,
+__global__ void k_keys(const InstDev* __restrict__ inst, StepParams sp,
+                       const double4* __restrict__ pos,
                        const double4* __restrict__ vel, int* __restrict__ info,
                        const double4* __restrict__ xref, int check_guard,
                        uint32_t* __restrict__ keys, int* __restrict__ rank,
@@ -85,8 +86,10 @@ __global__ void k_keys(GridDev g, StepParams sp, const double4* __restrict__ pos
   int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= sp.n) return;
   int inf = info[i];
-  uint32_t key = (uint32_t)g.n_keys;
+  uint32_t key = sp.n_keys;
   if (!(inf & kInactive)) {
+    const InstDev& I = inst[inf >> kInstShift];
+    const GridDev& g = I.grid;
     double4 p = pos[i];
     double4 v = vel[i];
     if (!finite3(p.x, p.y, p.z) || !finite3(v.x, v.y, v.z)) atomicOr(flags, kFlagNonFinite);
@@ -94,7 +97,7 @@ __global__ void k_keys(GridDev g, StepParams sp, const double4* __restrict__ pos
       double4 r = xref[i];
       double dx = p.x - r.x, dy = p.y - r.y, dz = p.z - r.z;
       double d2 = (dx * dx + dy * dy) + dz * dz;
-      if (d2 > sp.guard2) atomicOr(flags, kFlagGuard);
+      if (d2 > I.guard2) atomicOr(flags, kFlagGuard);
     }
     bool inside = p.x >= g.lo[0] && p.x < g.hi[0] && p.y >= g.lo[1] && p.y < g.hi[1] &&
                   p.z >= g.lo[2] && p.z < g.hi[2];
@@ -104,18 +107,18 @@ __global__ void k_keys(GridDev g, StepParams sp, const double4* __restrict__ pos
       int cx = cell_coord(p.x, g.lo[0], g.h, g.nc[0]);
       int cy = cell_coord(p.y, g.lo[1], g.h, g.nc[1]);
       int cz = cell_coord(p.z, g.lo[2], g.h, g.nc[2]);
-      key = cell_key(g, cx, cy, cz);
+      key = I.key_base + cell_key(g, cx, cy, cz);
     }
   }
   keys[i] = key;
   rank[i] = atomicAdd(&count[key], 1);
 }
 
-hipError_t launch_keys(const GridDev& g, const StepParams& sp, const double4* pos,
+hipError_t launch_keys(const InstDev* inst, const StepParams& sp, const double4* pos,
                        const double4* vel, int* info, const double4* xref, int check_guard,
                        uint32_t* keys, int* rank, int* count, int* flags, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_keys, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, g, sp, pos, vel, info,
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos, vel, info,
                      xref, check_guard, keys, rank, count, flags);
   return hipGetLastError();
 }
@@ -324,8 +327,8 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
 // Gather every particle array into sorted order, record the reference
 // position of the displacement guard, and redo the particle-wall search at
 // the new position carrying the tangential overlap of walls already listed.
-__global__ void k_reorder(StepParams sp, const int* __restrict__ perm, int* __restrict__ inv,
-                          ParticleBufs src,
+__global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
+                          const int* __restrict__ perm, int* __restrict__ inv, ParticleBufs src,
                           ParticleBufs dst, const int* __restrict__ gid_src,
                           int* __restrict__ gid_dst, const int* __restrict__ info_src,
                           int* __restrict__ info_dst, double4* __restrict__ xref,
@@ -352,10 +355,11 @@ __global__ void k_reorder(StepParams sp, const int* __restrict__ perm, int* __re
   }
   int c = 0;
   if (!(inf & kInactive)) {
+    const InstDev& I = inst[inf >> kInstShift];
     double x[3] = {ps.x, ps.y, ps.z};
-    for (int w = 0; w < sp.n_walls; ++w) {
+    for (int w = I.wall_begin; w < I.wall_end; ++w) {
       WallGeo g;
-      wall_geo(walls[w], x, ps.w, sp.skin, false, g);
+      wall_geo(walls[w], x, ps.w, I.skin, false, g);
       if (!g.candidate) continue;
       if (c == kWallSlots) {
         atomicOr(flags, kFlagWallOverflow);
@@ -382,14 +386,15 @@ __global__ void k_reorder(StepParams sp, const int* __restrict__ perm, int* __re
   for (; c < kWallSlots; ++c) ws_dst.wid[(int64_t)c * n + p] = -1;
 }
 
-hipError_t launch_reorder(const StepParams& sp, const int* perm, int* inv, ParticleBufs src,
-                          ParticleBufs dst, const int* gid_src, int* gid_dst,
+hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
+                          ParticleBufs src, ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, int* flags, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, perm, inv, src, dst,
+  hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, perm, inv,
+                     src, dst,
                      gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, F_src,
                      T_src, F_dst, T_dst, flags);
   return hipGetLastError();
@@ -406,17 +411,23 @@ hipError_t launch_reorder(const StepParams& sp, const int* perm, int* inv, Parti
 // was touching (bit 31) names its partner by old index; inv maps it to the new
 // index, which is looked up in the new row.  Entries without bit 31 have zero
 // history, which is therefore never stored.
-__global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ pos,
+__global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
+                         const double4* __restrict__ pos,
                          const int* __restrict__ info, const int* __restrict__ start,
                          const int* __restrict__ perm, const int* __restrict__ inv,
                          NbrList old_l, NbrList new_l, int* __restrict__ flags) {
   int p = xcd_block() * kBlock + threadIdx.x;
   if (p >= sp.n) return;
   const int max_nb = sp.max_nb;
-  if (info[p] & kInactive) {
+  const int inf = info[p];
+  if (inf & kInactive) {
     new_l.rowlen[p] = 0;
     return;
   }
+  const InstDev& I = inst[inf >> kInstShift];
+  const GridDev& g = I.grid;
+  const double rs2 = I.rs2;
+  const uint32_t kbase = I.key_base;
   const double4 pp = pos[p];
   const int cx = cell_coord(pp.x, g.lo[0], g.h, g.nc[0]);
   const int cy = cell_coord(pp.y, g.lo[1], g.h, g.nc[1]);
@@ -434,14 +445,14 @@ __global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ p
       for (int dx = -1; dx <= 1; ++dx) {
         const int x = cx + dx;
         if (x < 0 || x >= g.nc[0]) continue;
-        const uint32_t key = g.mort[0][x] | kyz;
+        const uint32_t key = kbase + (g.mort[0][x] | kyz);
         const int s = start[key], e = start[key + 1];
         for (int q = s; q < e; ++q) {
           if (q == p) continue;
           const double4 pq = pos[q];
           const double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
           const double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
-          if (!(d2 < sp.rs2)) continue;
+          if (!(d2 < rs2)) continue;
           if (front + back == max_nb) {
             overflow = true;
             continue;
@@ -483,11 +494,11 @@ __global__ void k_search(GridDev g, StepParams sp, const double4* __restrict__ p
   }
 }
 
-hipError_t launch_search(const GridDev& g, const StepParams& sp, const double4* pos,
+hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double4* pos,
                          const int* info, const int* start, const int* perm, const int* inv,
                          NbrList old_l, NbrList new_l, int* flags, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_search, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, g, sp, pos, info,
+  hipLaunchKernelGGL(k_search, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos, info,
                      start, perm, inv, old_l, new_l, flags);
   return hipGetLastError();
 }
@@ -706,7 +717,8 @@ constexpr int kIndexMask = 0x7fffffff;
 
 template <typename R, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
+k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
+        const PairCoef* __restrict__ pwc,
         const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
         const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
         double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
@@ -730,6 +742,9 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
     return;
   }
   const int ti = inf & kTypeMask;
+  const InstDev& I = inst[inf >> kInstShift];
+  const PairCoef* __restrict__ ppi = ppc + I.coef_base + ti * kMaxTypes;
+  const PairCoef* __restrict__ pwi = pwc + I.coef_base + ti * kMaxTypes;
   const double dt = sp.dt;
   double F[3] = {0.0, 0.0, 0.0};
   double T[3] = {0.0, 0.0, 0.0};
@@ -755,8 +770,7 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
         dtl[2] = l.hist[2 * cap + e];
       }
       double Fi[3], Mi[3];
-      pp_contact<R>(ppc[ti * kMaxTypes + tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi,
-                    Mi);
+      pp_contact<R>(ppi[tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       l.hist[e] = dtl[0];
       l.hist[cap + e] = dtl[1];
       l.hist[2 * cap + e] = dtl[2];
@@ -784,8 +798,7 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
                      ws.hist[(int64_t)(3 * s + 2) * n + i]};
     double Fi[3], Mi[3];
     if (t >= W.t_on && t < W.t_off) {
-      pw_contact<R>(pwc[ti * kMaxTypes + W.material], sp.rolling, dt, W, sp.skin, xi, vi, wi,
-                    dtl, Fi, Mi);
+      pw_contact<R>(pwi[W.material], sp.rolling, dt, W, I.skin, xi, vi, wi, dtl, Fi, Mi);
     } else {
       dtl[0] = dtl[1] = dtl[2] = 0.0;
       Fi[0] = Fi[1] = Fi[2] = 0.0;
@@ -847,7 +860,8 @@ k_force(StepParams sp, const PairCoef* __restrict__ ppc, const PairCoef* __restr
   }
 }
 
-hipError_t launch_force(int mode, int precision, const StepParams& sp, const PairCoef* pp,
+hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
+                        const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
@@ -855,8 +869,8 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Pai
   if (sp.n <= 0) return hipSuccess;
   dim3 gr(grid_for(sp.n)), bl(kBlock);
 #define DEM_LAUNCH(RT, M)                                                                   \
-  hipLaunchKernelGGL((k_force<RT, M>), gr, bl, 0, s, sp, pp, pw, walls, in, out, info, l, ws, \
-                     F, T, clock, step_rel, flags)
+  hipLaunchKernelGGL((k_force<RT, M>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, out, info, l, \
+                     ws, F, T, clock, step_rel, flags)
   if (precision == 0) {
     if (mode == 0) DEM_LAUNCH(double, 0);
     else if (mode == 1) DEM_LAUNCH(double, 1);

@@ -80,6 +80,8 @@ SIGNATURES = {
                                         C.c_double, C.c_double, I32P]),
     "dem_set_particles": (C.c_int, [P, C.c_int32, C.c_int64, DP, DP, DP, DP, I32P]),
     "dem_set_particles_device": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, P, P]),
+    "dem_commit": (C.c_int, [P]),
+    "dem_set_instance_domain": (C.c_int, [P, C.c_int32, DP, DP]),
     "dem_step": (C.c_int, [P, C.c_int64]),
     "dem_get_state": (C.c_int, [P, C.c_int32, DP, DP, DP, U8P, DP]),
     "dem_get_state_device": (C.c_int, [P, C.c_int32, P, P, P, P]),
@@ -129,7 +131,7 @@ class Dem:
     def __init__(self, dt, gravity=(0.0, 0.0, -9.81), domain_lo=(0, 0, 0), domain_hi=(1, 1, 1),
                  neighbor_threshold=1.3, cell_factor=None, rebuild_interval=20,
                  integrator="verlet", rolling_model="constant", precision="fp64",
-                 max_neighbors=0, hip_stream=None):
+                 max_neighbors=0, hip_stream=None, n_instances=1):
         self._lib = load_library()
         cfg = dem_config()
         cfg.dt = dt
@@ -142,12 +144,13 @@ class Dem:
         cfg.integrator = {"verlet": 0, "euler": 1}[integrator]
         cfg.rolling_model = {"none": 0, "constant": 1}[rolling_model]
         cfg.precision = {"fp64": 0, "fp32": 1}[precision]
-        cfg.n_instances = 1
+        cfg.n_instances = n_instances
         cfg.max_neighbors = max_neighbors
         cfg.hip_stream = hip_stream
         self._h = P()
         self._check(self._lib.dem_create(C.byref(cfg), C.byref(self._h)))
-        self.n = 0
+        self.n_instances = n_instances
+        self.counts = [0] * n_instances
         self.precision = precision
 
     # ------------------------------------------------------------ plumbing
@@ -168,31 +171,35 @@ class Dem:
             pass
 
     # ----------------------------------------------------------------- ABI
+    @property
+    def n(self):
+        return self.counts[0]
+
     def set_material(self, type_id, density, youngs, poisson, restitution, friction,
-                     rolling_friction):
+                     rolling_friction, instance=0):
         m = dem_material(density, youngs, poisson, restitution, friction, rolling_friction)
-        self._check(self._lib.dem_set_material(self._h, 0, type_id, C.byref(m)))
+        self._check(self._lib.dem_set_material(self._h, instance, type_id, C.byref(m)))
 
     def add_planar_wall(self, point, normal, material=0, extent=None, axis_point=None,
-                        omega=None, t_on=-np.inf, t_off=np.inf):
+                        omega=None, t_on=-np.inf, t_off=np.inf, instance=0):
         wid = C.c_int32()
         p, nr = _v3(point), _v3(normal)
         ext = None if extent is None else np.ascontiguousarray(extent, dtype=np.float64).reshape(5)
         ap, om = _v3(axis_point), _v3(omega)
-        self._check(self._lib.dem_add_planar_wall(self._h, 0, _d(p), _d(nr), _d(ext), material,
+        self._check(self._lib.dem_add_planar_wall(self._h, instance, _d(p), _d(nr), _d(ext), material,
                                                   _d(ap), _d(om), t_on, t_off, C.byref(wid)))
         return wid.value
 
     def add_cylinder_wall(self, axis_point, axis_dir, radius, s_min, s_max, inside=True,
-                          material=0, omega=0.0, t_on=-np.inf, t_off=np.inf):
+                          material=0, omega=0.0, t_on=-np.inf, t_off=np.inf, instance=0):
         wid = C.c_int32()
         ap, ad = _v3(axis_point), _v3(axis_dir)
-        self._check(self._lib.dem_add_cylinder_wall(self._h, 0, _d(ap), _d(ad), radius, s_min,
+        self._check(self._lib.dem_add_cylinder_wall(self._h, instance, _d(ap), _d(ad), radius, s_min,
                                                     s_max, 1 if inside else 0, material, omega,
                                                     t_on, t_off, C.byref(wid)))
         return wid.value
 
-    def set_particles(self, pos, radius, vel=None, omega=None, types=None):
+    def set_particles(self, pos, radius, vel=None, omega=None, types=None, instance=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         n = pos.shape[0]
         radius = np.ascontiguousarray(radius, dtype=np.float64).reshape(n)
@@ -200,15 +207,18 @@ class Dem:
         omega = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64).reshape(n, 3)
         tp = None if types is None else np.ascontiguousarray(types, dtype=np.int32).reshape(n)
         self._check(self._lib.dem_set_particles(
-            self._h, 0, n, _d(pos), _d(vel), _d(omega), _d(radius),
+            self._h, instance, n, _d(pos), _d(vel), _d(omega), _d(radius),
             None if tp is None else tp.ctypes.data_as(I32P)))
-        self.n = n
+        self.counts[instance] = n
 
     def set_particles_device(self, n, pos_ptr, radius_ptr, vel_ptr=None, omega_ptr=None,
-                             type_ptr=None):
-        self._check(self._lib.dem_set_particles_device(self._h, 0, n, pos_ptr, vel_ptr,
+                             type_ptr=None, instance=0):
+        self._check(self._lib.dem_set_particles_device(self._h, instance, n, pos_ptr, vel_ptr,
                                                        omega_ptr, radius_ptr, type_ptr))
-        self.n = n
+        self.counts[instance] = n
+
+    def commit(self):
+        self._check(self._lib.dem_commit(self._h))
 
     def step(self, n_steps=1):
         self._check(self._lib.dem_step(self._h, n_steps))
@@ -216,44 +226,45 @@ class Dem:
     def step_rc(self, n_steps=1):
         return self._lib.dem_step(self._h, n_steps)
 
-    def get_state(self):
-        n = self.n
+    def get_state(self, instance=0):
+        n = self.counts[instance]
         x = np.empty((n, 3)); v = np.empty((n, 3)); w = np.empty((n, 3))
         a = np.empty(n, dtype=np.uint8)
         t = C.c_double()
-        self._check(self._lib.dem_get_state(self._h, 0, _d(x), _d(v), _d(w),
+        self._check(self._lib.dem_get_state(self._h, instance, _d(x), _d(v), _d(w),
                                             a.ctypes.data_as(U8P), C.byref(t)))
         return {"pos": x, "vel": v, "omega": w, "active": a.astype(bool), "time": t.value}
 
     state = get_state
 
-    def get_forces(self):
-        F = np.empty((self.n, 3)); T = np.empty((self.n, 3))
-        self._check(self._lib.dem_get_forces(self._h, 0, _d(F), _d(T)))
+    def get_forces(self, instance=0):
+        n = self.counts[instance]
+        F = np.empty((n, 3)); T = np.empty((n, 3))
+        self._check(self._lib.dem_get_forces(self._h, instance, _d(F), _d(T)))
         return F, T
 
-    def get_contacts(self):
+    def get_contacts(self, instance=0):
         cnt = C.c_int64()
-        rc = self._lib.dem_get_contacts(self._h, 0, 0, None, None, None, C.byref(cnt))
+        rc = self._lib.dem_get_contacts(self._h, instance, 0, None, None, None, C.byref(cnt))
         if rc not in (DEM_OK, DEM_EINVAL):
             self._check(rc)
         m = cnt.value
         pairs = np.empty((max(m, 1), 2), dtype=np.int64)
         dt = np.empty((max(m, 1), 3))
         touch = np.empty(max(m, 1), dtype=np.uint8)
-        self._check(self._lib.dem_get_contacts(self._h, 0, max(m, 1), pairs.ctypes.data_as(I64P),
+        self._check(self._lib.dem_get_contacts(self._h, instance, max(m, 1), pairs.ctypes.data_as(I64P),
                                                _d(dt), touch.ctypes.data_as(U8P), C.byref(cnt)))
         return pairs[:m], dt[:m], touch[:m].astype(bool)
 
-    def get_wall_contacts(self):
+    def get_wall_contacts(self, instance=0):
         cnt = C.c_int64()
-        rc = self._lib.dem_get_wall_contacts(self._h, 0, 0, None, None, C.byref(cnt))
+        rc = self._lib.dem_get_wall_contacts(self._h, instance, 0, None, None, C.byref(cnt))
         if rc not in (DEM_OK, DEM_EINVAL):
             self._check(rc)
         m = cnt.value
         pairs = np.empty((max(m, 1), 2), dtype=np.int64)
         dt = np.empty((max(m, 1), 3))
-        self._check(self._lib.dem_get_wall_contacts(self._h, 0, max(m, 1),
+        self._check(self._lib.dem_get_wall_contacts(self._h, instance, max(m, 1),
                                                     pairs.ctypes.data_as(I64P), _d(dt),
                                                     C.byref(cnt)))
         return pairs[:m], dt[:m]
@@ -279,26 +290,55 @@ class Dem:
                 "searches": int(out[3])}
 
     # ------------------------------------------------------------- scenes
+    def set_instance_domain(self, lo, hi, instance=0):
+        lo, hi = _v3(lo), _v3(hi)
+        self._check(self._lib.dem_set_instance_domain(self._h, instance, _d(lo), _d(hi)))
+
+    def _add_scene(self, scene, instance, own_domain=False):
+        if own_domain:
+            self.set_instance_domain(scene["config"]["domain_lo"], scene["config"]["domain_hi"],
+                                     instance=instance)
+        for t, m in enumerate(scene["materials"]):
+            self.set_material(t, m["density"], m["youngs"], m["poisson"], m["restitution"],
+                              m["friction"], m["rolling_friction"], instance=instance)
+        for w in scene["walls"]:
+            if w["kind"] == "plane":
+                self.add_planar_wall(w["point"], w["normal"], w["material"], w.get("extent"),
+                                     w.get("axis_point"), w.get("omega"), w["t_on"], w["t_off"],
+                                     instance=instance)
+            else:
+                self.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
+                                       w["s_max"], w["inside"], w["material"], w["omega"],
+                                       w["t_on"], w["t_off"], instance=instance)
+        p = scene["particles"]
+        self.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"],
+                           instance=instance)
+
     @classmethod
     def from_scene(cls, scene, precision="fp64", max_neighbors=0, hip_stream=None):
         """Build a context from a scene dictionary (see ``workloads``)."""
-        c = scene["config"]
+        return cls.from_scenes([scene], precision, max_neighbors, hip_stream)
+
+    @classmethod
+    def from_scenes(cls, scenes, precision="fp64", max_neighbors=0, hip_stream=None):
+        """Build one batched context holding one instance per scene.  The scenes
+        must share dt, gravity, search settings and integrator; each keeps its
+        own domain box."""
+        c = scenes[0]["config"]
+
+        def shared(cfg):
+            return {k: v for k, v in cfg.items() if k not in ("domain_lo", "domain_hi")}
+        for s in scenes[1:]:
+            if shared(s["config"]) != shared(c):
+                raise ValueError("batched scenes must share their run configuration")
         sim = cls(dt=c["dt"], gravity=c["gravity"], domain_lo=c["domain_lo"],
                   domain_hi=c["domain_hi"], neighbor_threshold=c["neighbor_threshold"],
                   cell_factor=c["cell_factor"], rebuild_interval=c["rebuild_interval"],
                   integrator=c["integrator"], rolling_model=c["rolling_model"],
-                  precision=precision, max_neighbors=max_neighbors, hip_stream=hip_stream)
-        for t, m in enumerate(scene["materials"]):
-            sim.set_material(t, m["density"], m["youngs"], m["poisson"], m["restitution"],
-                             m["friction"], m["rolling_friction"])
-        for w in scene["walls"]:
-            if w["kind"] == "plane":
-                sim.add_planar_wall(w["point"], w["normal"], w["material"], w.get("extent"),
-                                    w.get("axis_point"), w.get("omega"), w["t_on"], w["t_off"])
-            else:
-                sim.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
-                                      w["s_max"], w["inside"], w["material"], w["omega"],
-                                      w["t_on"], w["t_off"])
-        p = scene["particles"]
-        sim.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"])
+                  precision=precision, max_neighbors=max_neighbors, hip_stream=hip_stream,
+                  n_instances=len(scenes))
+        for k, s in enumerate(scenes):
+            sim._add_scene(s, k, own_domain=len(scenes) > 1)
+        if len(scenes) > 1:
+            sim.commit()
         return sim

@@ -239,3 +239,26 @@ def dense_snapshot(n=3000, d=3.0e-3, seed=7, overlap=0.01, vmax=0.05, wmax=20.0,
                                                  rolling=rolling, integrator=integrator),
                 materials=mats, walls=wl,
                 particles=_particles(pts, radius, vel, om, types))
+
+
+def batched_drums(n_inst=256, n_min=2000, n_max=50000, d=3.0e-3, seed=4, dt=5.0e-6, K=20,
+                  threshold=1.3):
+    """Independent rotating drums of uneven size: per instance k (seeded by
+    SeedSequence(seed).spawn(n_inst)[k]) the particle count is log-uniform in
+    [n_min, n_max], the friction coefficient uniform in [0.1, 0.5], the drum
+    speed uniform in [0.5, 3] rad/s; the drum holds its spheres as a 35 % bulk
+    fill with length = 2 R.  Other material values are the drum material's."""
+    seqs = np.random.SeedSequence(seed).spawn(n_inst)
+    scenes = []
+    for k, ss in enumerate(seqs):
+        rng = np.random.Generator(np.random.PCG64(ss))
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        mu = float(rng.uniform(0.1, 0.5))
+        om = float(rng.uniform(0.5, 3.0))
+        lattice_seed = int(rng.integers(0, 2 ** 31 - 1))
+        mat = dict(DRUM_MATERIAL, friction=mu)
+        sc = drum_scene(n=n, d=d, omega=om, seed=lattice_seed, dt=dt, K=K, material=mat,
+                        threshold=threshold)
+        sc["name"] = f"drum{k}_{n}"
+        scenes.append(sc)
+    return scenes
