@@ -61,12 +61,14 @@ def load_traffic(precision):
     return None if e is None else float(e)
 
 
-def measure(args, precision, scene):
+def measure(args, precision, scene, label=None):
     import torch
     from paper_2106_09576_amd import Dem
 
+    precision_name = precision
+    precision = label or precision
     log(f"{precision}: uploading {scene['particles']['pos'].shape[0]} particles")
-    sim = Dem.from_scene(scene, precision=precision)
+    sim = Dem.from_scene(scene, precision=precision_name)
     stream = torch.cuda.ExternalStream(sim.stream())
     log(f"{precision}: warmup {args.warmup} steps (drum settles, contacts form)")
     done = 0
@@ -104,7 +106,7 @@ def measure(args, precision, scene):
     algo_bytes = BYTES_PER_PARTICLE * n_active + BYTES_PER_PAIR * pairs
     achieved = algo_bytes / (force_ms * 1e-3) / 1e9
     res = dict(
-        precision=precision,
+        precision=precision_name,
         value=n_active * args.steps / wall,
         ms_per_step=1e3 * wall / args.steps,
         event_ms_per_step=ev_ms / args.steps,
@@ -124,6 +126,41 @@ def measure(args, precision, scene):
     log(f"{precision}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step, "
         f"force kernel {force_ms:.4f} ms ({achieved:.0f} GB/s algorithmic)")
     sim.close()
+    return res
+
+
+def measure_batched(args, precision):
+    """The batched workload: 256 independent drums of uneven size (2k-50k
+    spheres, log-uniform) advanced together by every launch."""
+    import torch
+    import workloads as W
+    from paper_2106_09576_amd import Dem
+
+    scenes = W.batched_drums()
+    n = sum(s["particles"]["pos"].shape[0] for s in scenes)
+    log(f"batched {precision}: {len(scenes)} drums, {n} spheres")
+    sim = Dem.from_scenes(scenes, precision=precision)
+    done = 0
+    while done < args.batch_warmup:
+        k = min(args.batch_warmup - done, 5000)
+        sim.step(k)
+        done += k
+        log(f"batched {precision}: warmup {done}/{args.batch_warmup}")
+    st0 = sim.get_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.batch_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st1 = sim.get_stats()
+    n_active = 0.5 * (st0["n_active"] + st1["n_active"])
+    touching = 0.25 * (st0["n_touching"] + st1["n_touching"])
+    sim.close()
+    res = dict(precision=precision, instances=len(scenes), n_particles=n,
+               value=n_active * args.batch_steps / wall, ms_per_step=1e3 * wall / args.batch_steps,
+               contacts_per_s=touching * args.batch_steps / wall,
+               touching_per_particle=touching / max(n_active, 1))
+    log(f"batched {precision}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step")
     return res
 
 
@@ -154,6 +191,11 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-dynamic", action="store_true",
+                    help="skip the drum run with the displacement-triggered search")
+    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-warmup", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device copies of 1 GiB (read 1 GiB, write 1 GiB each), "
                          "to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -223,6 +265,24 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         out["mixed_vs_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if not args.skip_dynamic:
+        sc_dyn = dict(scene, config=dict(scene["config"], rebuild_interval=0))
+        dres = {p: measure(args, p, sc_dyn, label=f"{p} dynamic") for p in precs}
+        out["dynamic_search"] = {
+            "workload": "same drum, contact search triggered when a particle may have "
+                        "moved half the skin (rebuild_interval = 0)",
+            "results": dres,
+        }
+    if not args.skip_batched:
+        b = {p: measure_batched(args, p) for p in precs}
+        out["batched"] = {
+            "workload": ("256 independent rotating drums in one context, 2k-50k spheres each "
+                         "(log-uniform), d=3mm, mu U[0.1,0.5], 0.5-3 rad/s, 35% fill, dt=5e-6 s, "
+                         f"search every 20 steps, after {args.batch_warmup} settling steps"),
+            "results": b,
+        }
+        if "fp32" in b and "fp64" in b:
+            out["batched"]["fp32_vs_fp64"] = b["fp32"]["value"] / b["fp64"]["value"]
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline(args, scene)
     print(json.dumps(out), flush=True)

@@ -72,7 +72,10 @@ typedef struct {
   double neighbor_threshold; /* r_s / d_max (paper default 1.3, Sec. 3.2) */
   double cell_factor;        /* cell edge h / d_max; r_s = min(threshold,
                                 cell_factor) * d_max, so h >= r_s always */
-  int32_t rebuild_interval;  /* K: contact search every K steps (Sec. 3.1) */
+  int32_t rebuild_interval;  /* K >= 1: contact search every K steps
+                                (Sec. 3.1); 0 = dynamic: search when a
+                                particle may have moved half the skin
+                                r_s - d_max since the last search */
   int32_t integrator;        /* 0 velocity Verlet (Eqs. halfstep/newvv),
                                 1 explicit Euler (Eq. integ_EE) */
   int32_t rolling_model;     /* 0 none, 1 constant torque (Sec. 2.1 table) */
@@ -103,7 +106,7 @@ typedef struct {
 } dem_stats;
 
 /* Create a context on the current HIP device.  cfg is copied.  Fails with
-   DEM_EINVAL for dt <= 0, an empty domain, rebuild_interval < 1, threshold or
+   DEM_EINVAL for dt <= 0, an empty domain, rebuild_interval < 0, threshold or
    cell_factor < 1, an unknown integrator/rolling model/precision or
    n_instances outside [1, 2048]; DEM_ENODEV if the device is not gfx950. */
 int dem_create(const dem_config* cfg, dem_ctx** out_ctx);
@@ -175,8 +178,13 @@ int dem_set_instance_domain(dem_ctx* ctx, int32_t instance, const double lo[3],
 int dem_commit(dem_ctx* ctx);
 
 /* Advance every instance by n_steps >= 0 steps.  Synchronous: returns after the work finished.
-   Contact searches run at every step number that is a multiple of
-   rebuild_interval.  Errors (DEM_EUNSTABLE, DEM_ECAPACITY) are sticky: the
+   With rebuild_interval K >= 1, contact searches run at every step number
+   that is a multiple of K.  With K = 0 the library reads back, every few
+   steps, the largest per-step displacement |v| dt of any particle and
+   searches before the summed bound could reach half the skin; a missed
+   bound still trips the displacement check of the next search
+   (DEM_EUNSTABLE).  dem_commit with K = 0 fails with DEM_EINVAL when an
+   instance has no skin (neighbor_threshold = 1).  Errors (DEM_EUNSTABLE, DEM_ECAPACITY) are sticky: the
    state is frozen at the step where they were detected and later dem_step
    calls return DEM_ESTATE until dem_set_particles is called again. */
 int dem_step(dem_ctx* ctx, int64_t n_steps);

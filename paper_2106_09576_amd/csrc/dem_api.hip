@@ -28,6 +28,8 @@ namespace {
 thread_local std::string g_err;
 
 constexpr double kPi = 3.14159265358979323846;
+// dynamic search: steps per chunk between two host decisions
+constexpr int kDynChunk = 16;
 
 int set_err(int code, const char* fmt, ...) {
   char buf[512];
@@ -107,6 +109,17 @@ struct dem_ctx {
   int64_t n_rebuilds = 0;
   hipGraphExec_t graph[2][2]{};
 
+  // dynamic search trigger (rebuild_interval == 0): every force launch raises
+  // drift[slot] to its largest drift in half skins; the host keeps a bound on
+  // the largest displacement since the last search and the last step rate
+  bool dynamic = false;
+  unsigned long long* d_drift = nullptr;  // kDynChunk + 1 records of kDriftSpread words
+  unsigned long long* h_drift = nullptr;  // pinned host copy
+  double dyn_acc = 0.0;
+  double dyn_rate = 0.0;
+  double dyn_grav = 0.0;  // |g| dt^2 (2/skin)max: growth of the rate per step
+  hipGraphExec_t dyn_graph[2][2][2]{};  // [cur][pcur][chunk starts with a search]
+
   // optional per-kernel timing (benchmarks): events around force launches
   bool timing = false;
   std::vector<hipEvent_t> tev;
@@ -143,16 +156,26 @@ int dalloc_t(dem_ctx* c, T** p, size_t count) {
 
 void destroy_graphs(dem_ctx* c) {
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
       if (c->graph[a][b]) {
         (void)hipGraphExecDestroy(c->graph[a][b]);
         c->graph[a][b] = nullptr;
       }
+      for (int r = 0; r < 2; ++r)
+        if (c->dyn_graph[a][b][r]) {
+          (void)hipGraphExecDestroy(c->dyn_graph[a][b][r]);
+          c->dyn_graph[a][b][r] = nullptr;
+        }
+    }
 }
 
 void free_particles(dem_ctx* c) {
   destroy_graphs(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->h_drift) {
+    (void)hipHostFree(c->h_drift);
+    c->h_drift = nullptr;
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   c->dev_bytes = 0;
@@ -247,12 +270,12 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
   return DEM_OK;
 }
 
-int enqueue_force(dem_ctx* c, int mode, int64_t step_rel) {
+int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* drift = nullptr) {
   const int a = c->cur, p = c->pcur;
   HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_inst, c->d_pp, c->d_pw, c->d_walls,
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
-                      c->d_clock, step_rel, c->d_flags, c->stream));
+                      c->d_clock, step_rel, c->d_flags, drift, c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }
@@ -308,10 +331,10 @@ int eager_rebuild(dem_ctx* c) {
   return timed_end(c);
 }
 
-int eager_force(dem_ctx* c, int mode, int64_t step_rel) {
+int eager_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* drift = nullptr) {
   int rc = timed_begin(c, 0);
   if (rc) return rc;
-  rc = enqueue_force(c, mode, step_rel);
+  rc = enqueue_force(c, mode, step_rel, drift);
   if (rc) return rc;
   return timed_end(c);
 }
@@ -379,6 +402,141 @@ int launch_chunk(dem_ctx* c, int64_t clock_at_start) {
   c->pcur ^= 1;
   c->n_rebuilds += 1;
   c->host_base += K;
+  return DEM_OK;
+}
+
+// ------------------------------------------------- dynamic search trigger
+//
+// "dynamic" contact detection (Sec. 3.1): search when particles may have
+// moved far enough to miss a contact.  Steps run in chunks of at most
+// kDynChunk.  Before a chunk the host knows acc, a bound on the largest
+// displacement since the last search (sum over steps of the largest drift),
+// and rate, the largest drift of one step in the last chunk, both in units of
+// half the skin.  The chunk starts with a search when acc + 2 L rate' could
+// reach 1 (rate' = rate plus what gravity adds over the chunk); after it the
+// per-step maxima are read back.  The displacement guard of every search
+// still checks the true displacement.
+
+int enqueue_dyn_chunk(dem_ctx* c, int L, bool search, bool last_is_call_end) {
+  const int vv = c->cfg.integrator == 0;
+  HIPCHK(launch_fill_i32((int*)(c->d_drift + kDriftSpread), 0, 2 * kDriftSpread * (int64_t)L,
+                         c->stream));
+  if (search) {
+    int rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
+    if (rc) return rc;
+  }
+  for (int j = 0; j < L; ++j) {
+    const int mode = vv ? ((last_is_call_end && j == L - 1) ? 1 : 0) : 2;
+    int rc = enqueue_force(c, mode, j, c->d_drift + (size_t)kDriftSpread * (1 + j));
+    if (rc) return rc;
+  }
+  return DEM_OK;
+}
+
+int get_dyn_graph(dem_ctx* c, bool search, hipGraphExec_t* out) {
+  hipGraphExec_t& g = c->dyn_graph[c->cur][c->pcur][search ? 1 : 0];
+  if (g) {
+    *out = g;
+    return DEM_OK;
+  }
+  const int save_cur = c->cur, save_pcur = c->pcur;
+  const int64_t save_rb = c->n_rebuilds;
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = enqueue_dyn_chunk(c, kDynChunk, search, false);
+  if (rc == DEM_OK) {
+    hipError_t e = launch_tick(c->d_clock, kDynChunk, c->stream);
+    if (e != hipSuccess) rc = set_err(DEM_EHIP, "tick launch: %s", hipGetErrorString(e));
+  }
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->cur = save_cur;
+  c->pcur = save_pcur;
+  c->n_rebuilds = save_rb;
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return set_err(DEM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g = nullptr;
+    return set_err(DEM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  *out = g;
+  return DEM_OK;
+}
+
+// read back drift records [first, first + count) and fold them into the bound
+int fold_drift(dem_ctx* c, int first, int count) {
+  const size_t w0 = (size_t)kDriftSpread * first, nw = (size_t)kDriftSpread * count;
+  HIPCHK(hipMemcpyAsync(c->h_drift + w0, c->d_drift + w0, sizeof(unsigned long long) * nw,
+                        hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double rate = 0.0;
+  for (int k = first; k < first + count; ++k) {
+    double v2 = 0.0;  // the device keeps the largest square, spread over words
+    for (int w = 0; w < kDriftSpread; ++w) {
+      double x;
+      memcpy(&x, &c->h_drift[(size_t)kDriftSpread * k + w], sizeof(double));
+      v2 = std::max(v2, x);
+    }
+    const double v = std::sqrt(v2);
+    c->dyn_acc += v;
+    rate = std::max(rate, v);
+  }
+  if (count > 0) c->dyn_rate = rate;
+  return DEM_OK;
+}
+
+int step_dynamic(dem_ctx* c, int64_t n_steps) {
+  const bool vv = c->cfg.integrator == 0;
+  const int64_t s0 = c->step, s_end = s0 + n_steps;
+  const bool graphs = !c->timing;
+  int rc = DEM_OK;
+  if (vv) {
+    HIPCHK(launch_fill_i32((int*)c->d_drift, 0, 2 * kDriftSpread, c->stream));
+    HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
+                             c->F[c->pcur], c->T[c->pcur], c->d_drift, c->stream));
+    if ((rc = fold_drift(c, 0, 1))) return rc;
+  }
+  int64_t s = s0 + 1;
+  while (s <= s_end) {
+    int L = (int)std::min<int64_t>(kDynChunk, s_end - s + 1);
+    // keep one chunk's worth of predicted drift below half a skin
+    const double rate = c->dyn_rate + c->dyn_grav * L;
+    while (L > 1 && 2.0 * L * rate >= 0.5) --L;
+    const double pred = 2.0 * L * (c->dyn_rate + c->dyn_grav * L);
+    const bool search = c->dyn_acc + pred >= 1.0;
+    if (search) c->dyn_acc = 0.0;
+    const bool call_end = s + L - 1 == s_end;
+    if (graphs && L == kDynChunk && !call_end) {
+      if ((rc = set_clock(c, s - (vv ? 0 : 1)))) return rc;
+      hipGraphExec_t g = nullptr;
+      if ((rc = get_dyn_graph(c, search, &g))) return rc;
+      HIPCHK(hipGraphLaunch(g, c->stream));
+      c->cur ^= (kDynChunk + (search ? 1 : 0)) & 1;
+      if (search) {
+        c->pcur ^= 1;
+        c->n_rebuilds += 1;
+      }
+      c->host_base += kDynChunk;
+    } else {
+      // eager: the clock stays, the step offset is explicit
+      const int64_t base = (vv ? s : s - 1) - c->host_base;
+      HIPCHK(launch_fill_i32((int*)(c->d_drift + kDriftSpread), 0,
+                             2 * kDriftSpread * (int64_t)L, c->stream));
+      if (search && (rc = eager_rebuild(c))) return rc;
+      for (int j = 0; j < L; ++j) {
+        const int mode = vv ? ((call_end && j == L - 1) ? 1 : 0) : 2;
+        unsigned long long* rec = c->d_drift + (size_t)kDriftSpread * (1 + j);
+        if ((rc = eager_force(c, mode, base + j, rec))) return rc;
+      }
+    }
+    // the last force launch of a Verlet call does not drift
+    if ((rc = fold_drift(c, 1, vv && call_end ? L - 1 : L))) return rc;
+    s += L;
+  }
   return DEM_OK;
 }
 
@@ -514,6 +672,31 @@ int commit(dem_ctx* c) {
     I.w_begin = n_walls;
     n_walls += (int)I.walls.size();
   }
+  c->dynamic = c->cfg.rebuild_interval == 0;
+  double ihs_max = 0.0, rate0 = 0.0, ihs_min = HUGE_VAL;
+  if (c->dynamic) {
+    for (int b = 0; b < B; ++b) {
+      const Instance& I = c->inst[(size_t)b];
+      if (I.n == 0) continue;
+      if (!(I.skin > 0.0))
+        return set_err(DEM_EINVAL,
+                       "dynamic search (rebuild_interval 0) needs a skin: neighbor_threshold "
+                       "and cell_factor must exceed 1");
+      const double ihs = 2.0 / I.skin;
+      ihs_max = std::max(ihs_max, ihs);
+      ihs_min = std::min(ihs_min, ihs);
+      for (int64_t i = 0; i < I.n && !I.vel.empty(); ++i) {
+        const double* v = &I.vel[3 * (size_t)i];
+        rate0 = std::max(rate0, sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]) * c->cfg.dt * ihs);
+      }
+    }
+  }
+  const double gmag = sqrt((c->cfg.gravity[0] * c->cfg.gravity[0] +
+                            c->cfg.gravity[1] * c->cfg.gravity[1]) +
+                           c->cfg.gravity[2] * c->cfg.gravity[2]);
+  c->dyn_acc = 0.0;
+  c->dyn_rate = rate0;
+  c->dyn_grav = gmag * c->cfg.dt * c->cfg.dt * ihs_max;
   int max_nb = c->cfg.max_neighbors;
   if (max_nb == 0) max_nb = (int)std::min(512.0, ceil(bound_nb));
   c->max_nb = max_nb;
@@ -530,6 +713,7 @@ int commit(dem_ctx* c) {
   sp.max_nb = max_nb;
   sp.rolling = c->cfg.rolling_model;
   sp.n_keys = (uint32_t)total_keys;
+  sp.drift_scale = ihs_min == ihs_max ? c->cfg.dt * ihs_max : 0.0;
 
   // allocations
   const size_t NN = (size_t)std::max<int64_t>(N, 1);
@@ -566,6 +750,16 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
   uint32_t* d_mort = nullptr;
   rc = rc ? rc : dalloc_t(c, &d_mort, std::max<size_t>(mort_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
+  if (rc == DEM_OK) {
+    hipError_t he = hipHostMalloc((void**)&c->h_drift,
+                                  sizeof(unsigned long long) * kDriftSpread * (kDynChunk + 1),
+                                  hipHostMallocDefault);
+    if (he != hipSuccess) {
+      c->h_drift = nullptr;
+      rc = set_err(DEM_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(he));
+    }
+  }
   if (rc) {
     free_particles(c);
     return rc;
@@ -608,7 +802,11 @@ int commit(dem_ctx* c) {
     D.rs2 = I.rs * I.rs;
     D.guard2 = (0.5 * I.skin) * (0.5 * I.skin);
     D.skin = I.skin;
-    hwalls.insert(hwalls.end(), I.walls.begin(), I.walls.end());
+    D.ihs = I.skin > 0.0 ? 2.0 / I.skin : 0.0;
+    for (WallDev w : I.walls) {
+      w.skin = I.skin;
+      hwalls.push_back(w);
+    }
     for (int ta = 0; ta < kMaxTypes; ++ta)
       for (int tb = 0; tb < kMaxTypes; ++tb) {
         if (!I.mat_set[ta] || !I.mat_set[tb]) continue;
@@ -707,7 +905,8 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
   for (int k = 0; k < 3; ++k)
     if (!(cfg->domain_hi[k] > cfg->domain_lo[k]))
       return set_err(DEM_EINVAL, "empty domain along axis %d", k);
-  if (cfg->rebuild_interval < 1) return set_err(DEM_EINVAL, "rebuild_interval must be >= 1");
+  if (cfg->rebuild_interval < 0)
+    return set_err(DEM_EINVAL, "rebuild_interval must be >= 1 (constant) or 0 (dynamic)");
   if (!(cfg->neighbor_threshold >= 1.0))
     return set_err(DEM_EINVAL, "neighbor_threshold must be >= 1");
   if (!(cfg->cell_factor >= 1.0)) return set_err(DEM_EINVAL, "cell_factor must be >= 1");
@@ -942,12 +1141,20 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
   }
   int rc = wait_user(c);
   if (rc) return rc;
+  if (c->dynamic) {
+    if ((rc = step_dynamic(c, n_steps))) return rc;
+    c->step += n_steps;
+    int flags = 0;
+    if ((rc = read_flags(c, &flags))) return rc;
+    if ((rc = collect_timing(c))) return rc;
+    return flags_to_error(c, flags);
+  }
   const int64_t K = c->cfg.rebuild_interval;
   const int64_t s0 = c->step, s_end = s0 + n_steps;
   const bool graphs = !c->timing;
   if (c->cfg.integrator == 0) {
-    HIPCHK(launch_kick_drift(c->sp, pbufs(c, c->cur), c->info[c->pcur], c->F[c->pcur],
-                             c->T[c->pcur], c->stream));
+    HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
+                             c->F[c->pcur], c->T[c->pcur], nullptr, c->stream));
     int64_t s = s0 + 1;
     while (s <= s_end) {
       if (graphs && s % K == 0 && s + K - 1 <= s_end - 1) {

@@ -15,6 +15,7 @@ constexpr int kWave = 64;
 constexpr int kTypeMask = 0xffff;
 constexpr int kInactive = 1 << 16;  // flag bit in the per-particle info word
 constexpr int kInstShift = 20;      // info bits 20..30: instance of the particle
+constexpr int kDriftSpread = 32;  // words per drift record
 constexpr int kMaxInstances = 2048;
 
 // Sticky error bits raised by kernels (read once per dem_step call).
@@ -46,6 +47,7 @@ struct WallDev {
   double hu, hv, radius, smin, smax;
   double omega[3], ax[3];
   double t_on, t_off;
+  double skin;  // the owning instance's skin (contact-search margin)
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).
@@ -72,6 +74,7 @@ struct InstDev {
   double rs2;     // squared search radius
   double guard2;  // (skin/2)^2
   double skin;    // r_s - d_max
+  double ihs;     // 2 / skin (drift in units of half the skin)
 };
 
 struct StepParams {
@@ -81,6 +84,8 @@ struct StepParams {
   int max_nb;      // neighbour slots per particle
   int rolling;     // 0 none, 1 constant torque
   uint32_t n_keys; // total cell keys; key n_keys collects inactive particles
+  double drift_scale;  // dt * 2 / skin when every instance has the same skin,
+                       // else 0 (then taken per particle from its instance)
 };
 
 // Particle arrays in sorted (spatial) order.  pos = (x, y, z, R),
@@ -147,10 +152,16 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, hipStream_t s);
-// first half kick + drift from stored forces (start of a velocity-Verlet call)
-hipError_t launch_kick_drift(const StepParams& sp, ParticleBufs st, const int* info,
-                             const double4* F, const double4* T, hipStream_t s);
+                        const int* flags, unsigned long long* drift, hipStream_t s);
+// first half kick + drift from stored forces (start of a velocity-Verlet call).
+// When drift is not null, both launchers raise the kDriftSpread words at
+// drift (as the bits of non-negative doubles) so that their maximum is the
+// largest squared drift |v| dt of the step, in units of half the particle's
+// skin (each wavefront raises one word: spreading the atomics over several
+// words keeps them from queueing on one address).
+hipError_t launch_kick_drift(const StepParams& sp, const InstDev* inst, ParticleBufs st,
+                             const int* info, const double4* F, const double4* T,
+                             unsigned long long* drift, hipStream_t s);
 hipError_t launch_tick(int64_t* clock, int64_t k, hipStream_t s);
 // statistics: out[0] active, [1] list entries, [2] touching entries, [3] wall slots
 hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* info,

@@ -715,17 +715,31 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, doubl
 constexpr int kTouchedBit = (int)0x80000000u;
 constexpr int kIndexMask = 0x7fffffff;
 
+// Square of a step's drift |v| dt in units of half the skin: scale = dt * 2 /
+// skin.  Maxima of squares are taken on the device, the root on the host.
+__device__ __forceinline__ double drift2(const double4& v, double scale) {
+  const double s2 = scale * scale;
+  return ((v.x * v.x + v.y * v.y) + v.z * v.z) * s2;
+}
+
+// dt * 2 / skin of the particle's instance (uniform when all skins agree)
+__device__ __forceinline__ double drift_scale(const StepParams& sp,
+                                              const InstDev* __restrict__ inst, int inf) {
+  return sp.drift_scale > 0.0 ? sp.drift_scale : sp.dt * inst[inf >> kInstShift].ihs;
+}
+
+// Forces on particle i and its integration; returns the squared drift of
+// this step in units of half the instance's skin (for the dynamic search
+// trigger) when asked for it.
 template <typename R, int MODE>
-__global__ void __launch_bounds__(kBlock)
-k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
-        const PairCoef* __restrict__ pwc,
-        const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
-        const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
-        double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
-        const int* __restrict__ flags) {
-  const int i = xcd_block() * kBlock + threadIdx.x;
+__device__ __forceinline__ double force_particle(
+    const int i, const StepParams& sp, const InstDev* __restrict__ inst,
+    const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
+    const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
+    const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
+    double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
+    const int* __restrict__ flags, const bool want_drift) {
   const int n = sp.n;
-  if (i >= n) return;
   double4 xi = in.pos[i];
   double4 vi = in.vel[i];
   double4 wi = in.omg[i];
@@ -739,12 +753,14 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
       Fo[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       To[i] = make_double4(0.0, 0.0, 0.0, 0.0);
     }
-    return;
+    return 0.0;
   }
+  // material-pair row of (instance, type i): instance b's table starts at
+  // b * kMaxTypes^2, so it follows from the info word without a lookup
   const int ti = inf & kTypeMask;
-  const InstDev& I = inst[inf >> kInstShift];
-  const PairCoef* __restrict__ ppi = ppc + I.coef_base + ti * kMaxTypes;
-  const PairCoef* __restrict__ pwi = pwc + I.coef_base + ti * kMaxTypes;
+  const int row = ((inf >> kInstShift) * kMaxTypes + ti) * kMaxTypes;
+  const PairCoef* __restrict__ ppi = ppc + row;
+  const PairCoef* __restrict__ pwi = pwc + row;
   const double dt = sp.dt;
   double F[3] = {0.0, 0.0, 0.0};
   double T[3] = {0.0, 0.0, 0.0};
@@ -798,7 +814,7 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
                      ws.hist[(int64_t)(3 * s + 2) * n + i]};
     double Fi[3], Mi[3];
     if (t >= W.t_on && t < W.t_off) {
-      pw_contact<R>(pwi[W.material], sp.rolling, dt, W, I.skin, xi, vi, wi, dtl, Fi, Mi);
+      pw_contact<R>(pwi[W.material], sp.rolling, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
     } else {
       dtl[0] = dtl[1] = dtl[2] = 0.0;
       Fi[0] = Fi[1] = Fi[2] = 0.0;
@@ -818,8 +834,10 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   const double im = vi.w, iI = wi.w;
   const double a[3] = {F[0] * im + sp.g[0], F[1] * im + sp.g[1], F[2] * im + sp.g[2]};
   const double al[3] = {T[0] * iI, T[1] * iI, T[2] * iI};
+  double drift = 0.0;
   if (MODE == 2) {
     // explicit Euler, Eq. (integ_EE): x with the old velocity
+    if (want_drift) drift = drift2(vi, drift_scale(sp, inst, inf));
     xi.x = xi.x + vi.x * dt;
     xi.y = xi.y + vi.y * dt;
     xi.z = xi.z + vi.z * dt;
@@ -849,6 +867,7 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
       xi.x = xi.x + vi.x * dt;
       xi.y = xi.y + vi.y * dt;
       xi.z = xi.z + vi.z * dt;
+      if (want_drift) drift = drift2(vi, drift_scale(sp, inst, inf));
     }
   }
   out.pos[i] = xi;
@@ -858,6 +877,33 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
     Fo[i] = make_double4(F[0], F[1], F[2], 0.0);
     To[i] = make_double4(T[0], T[1], T[2], 0.0);
   }
+  return drift;
+}
+
+// Largest value of a wavefront (shuffles), then one atomic per wavefront on
+// one of kDriftSpread words: non-negative doubles order like their bit
+// patterns.  Every lane of the wavefront calls it.
+__device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  const int w = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kDriftSpread - 1);
+  if ((threadIdx.x & 63) == 0 && v > 0.0)
+    atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename R, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
+        const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
+        ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
+        double4* __restrict__ Fo, double4* __restrict__ To, const int64_t* __restrict__ clock,
+        int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift) {
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  double d = 0.0;
+  if (i < sp.n)
+    d = force_particle<R, MODE>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo, To,
+                                clock, step_rel, flags, drift != nullptr);
+  if (drift) wave_max_to(drift, d);
 }
 
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
@@ -865,12 +911,12 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, hipStream_t s) {
+                        const int* flags, unsigned long long* drift, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   dim3 gr(grid_for(sp.n)), bl(kBlock);
 #define DEM_LAUNCH(RT, M)                                                                   \
   hipLaunchKernelGGL((k_force<RT, M>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, out, info, l, \
-                     ws, F, T, clock, step_rel, flags)
+                     ws, F, T, clock, step_rel, flags, drift)
   if (precision == 0) {
     if (mode == 0) DEM_LAUNCH(double, 0);
     else if (mode == 1) DEM_LAUNCH(double, 1);
@@ -886,11 +932,12 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
 
 // ------------------------------------------------------ kick-drift, clock
 
-__global__ void k_kick_drift(StepParams sp, ParticleBufs st, const int* __restrict__ info,
-                             const double4* __restrict__ F, const double4* __restrict__ T) {
-  int i = xcd_block() * kBlock + threadIdx.x;
-  if (i >= sp.n) return;
-  if (info[i] & kInactive) return;
+// first half kick and drift of particle i from the stored forces; returns the
+// squared drift in units of half the skin when asked for it
+__device__ __forceinline__ double kick_drift_one(int i, const StepParams& sp, const InstDev* __restrict__ inst,
+                                 ParticleBufs st, const int* __restrict__ info,
+                                 const double4* __restrict__ F,
+                                 const double4* __restrict__ T, const bool want_drift) {
   double4 x = st.pos[i], v = st.vel[i], w = st.omg[i];
   double4 f = F[i], tq = T[i];
   const double h = sp.hdt, dt = sp.dt;
@@ -908,14 +955,30 @@ __global__ void k_kick_drift(StepParams sp, ParticleBufs st, const int* __restri
   st.pos[i] = x;
   st.vel[i] = v;
   st.omg[i] = w;
+  if (!want_drift) return 0.0;
+  return drift2(v, drift_scale(sp, inst, info[i]));
 }
 
-hipError_t launch_kick_drift(const StepParams& sp, ParticleBufs st, const int* info,
-                             const double4* F, const double4* T, hipStream_t s) {
+__global__ void k_kick_drift(StepParams sp, const InstDev* __restrict__ inst, ParticleBufs st,
+                             const int* __restrict__ info, const double4* __restrict__ F,
+                             const double4* __restrict__ T,
+                             unsigned long long* __restrict__ drift) {
+  int i = xcd_block() * kBlock + threadIdx.x;
+  double d = 0.0;
+  if (i < sp.n && !(info[i] & kInactive)) d = kick_drift_one(i, sp, inst, st, info, F, T, drift != nullptr);
+  if (drift) wave_max_to(drift, d);
+}
+
+hipError_t launch_kick_drift(const StepParams& sp, const InstDev* inst, ParticleBufs st,
+                             const int* info, const double4* F, const double4* T,
+                             unsigned long long* drift, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, st, info, F, T);
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, st, info,
+                     F, T, drift);
   return hipGetLastError();
 }
+
+
 
 __global__ void k_tick(int64_t* clock, int64_t k) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] += k;

@@ -103,3 +103,48 @@ def test_batch_of_256_uneven_drums_runs_and_sampled_instances_match(Dem):
         assert np.array_equal(gp, op) and np.array_equal(gt, ot), k
         d = 2 * scenes[k]["particles"]["radius"][0]
         assert np.max(np.abs(batch.get_state(k)["pos"] - o.state()["pos"])) <= 1e-6 * d
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_dynamic_search_with_different_skins(Dem, precision):
+    """Dynamic search in a batch whose instances have different particle
+    sizes, hence different skins: each instance still follows the oracle
+    searching at every step, and equals its own single dynamic run."""
+    scenes = [W.drum_scene(n=n, d=d, omega=om, seed=s, dt=1e-5, K=0)
+              for n, d, om, s in ((900, 3e-3, 2.0, 1), (1500, 2e-3, 3.0, 2), (400, 4e-3, 1.0, 3))]
+    rng = np.random.default_rng(8)
+    for sc in scenes:  # random motion, so that spheres collide and searches are due
+        sc["particles"]["vel"] = rng.normal(0.0, 0.2, sc["particles"]["pos"].shape)
+    batch = Dem.from_scenes(scenes, precision=precision)
+    batch.step(150)
+    batch.step(90)
+    assert batch.get_stats()["n_rebuilds"] < 240 / 4
+    for k, sc in enumerate(scenes):
+        one = Dem.from_scene(sc, precision=precision)
+        one.step(150)
+        one.step(90)
+        a, b = batch.get_state(k), one.get_state()
+        # the batch searches when its fastest instance needs it: contact sets,
+        # hence trajectories, agree; summation orders may differ (re-sorts)
+        d = 2 * sc["particles"]["radius"][0]
+        assert np.max(np.abs(a["pos"] - b["pos"])) <= 1e-9 * d
+        o = oracle_from_scene(dict(sc, config=dict(sc["config"], rebuild_interval=1)))
+        o.step(240)
+        gp, gd, gt = batch.get_contacts(k)
+        op, od, ot = o.contacts()
+        gtp = {tuple(p) for p, t in zip(gp, gt) if t}
+        otp = {tuple(p) for p, t in zip(op, ot) if t}
+        assert gtp == otp, k
+        err = np.max(np.abs(a["pos"] - o.state()["pos"]))
+        if precision == "fp64":
+            assert err <= 1e-12, k
+        else:
+            # colliding spheres amplify the FP32 law's rounding; the search
+            # schedule must add nothing to it: compare with searching every step
+            k1 = Dem.from_scene(dict(sc, config=dict(sc["config"], rebuild_interval=1)),
+                                precision=precision)
+            k1.step(240)
+            err1 = np.max(np.abs(k1.get_state()["pos"] - o.state()["pos"]))
+            assert err <= 5 * err1 + 1e-15, (k, err, err1)
+            k1.close()
+        one.close()

@@ -349,3 +349,67 @@ def test_drum_1m_forces_and_sets_after_steps(drum_pair):
     st = g.get_stats()
     print("drum stats", st, flush=True)
     assert st["n_active"] == 1_000_000
+
+
+# ------------------------------------------------------- dynamic search trigger
+
+@pytest.mark.parametrize("integrator", ["verlet", "euler"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dynamic_search_matches_oracle_searching_every_step(Dem, integrator, precision):
+    """With rebuild_interval = 0 the library searches only when particles may
+    have moved half a skin; as no contact is missed, the trajectory equals the
+    oracle's with a search at every step (the search schedule cannot change
+    the physics, Sec. 3.1)."""
+    sc = W.dense_snapshot(n=1500, seed=23, integrator=integrator, K=1)
+    o = oracle_from_scene(sc)
+    o.radius = sc["particles"]["radius"]
+    sc_dyn = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+    g = Dem.from_scene(sc_dyn, precision=precision)
+    for chunk in (7, 40, 153):
+        g.step(chunk)
+        o.step(chunk)
+    st = g.get_stats()
+    assert st["n_rebuilds"] < 200 / 4  # far fewer searches than steps
+    err = np.max(np.abs(g.get_state()["pos"] - o.state()["pos"]))
+    if precision == "fp64":
+        assert err <= 1e-12
+    else:
+        # this jammed snapshot amplifies the FP32 law's rounding; the search
+        # schedule must add nothing to it: compare with searching every step
+        g1 = Dem.from_scene(sc, precision=precision)
+        g1.step(200)
+        err1 = np.max(np.abs(g1.get_state()["pos"] - o.state()["pos"]))
+        assert err <= 5 * err1 + 1e-15, (err, err1)
+        assert err <= 1e-5 * 3e-3
+    # touching pairs and their histories agree (the candidate lists differ)
+    gp, gd, gt = g.get_contacts()
+    op, od, ot = o.contacts()
+    gtp = {tuple(p): d for p, d, t in zip(gp, gd, gt) if t}
+    otp = {tuple(p): d for p, d, t in zip(op, od, ot) if t}
+    assert gtp.keys() == otp.keys()
+    if precision == "fp64":
+        for k in otp:
+            assert np.max(np.abs(gtp[k] - otp[k])) <= 1e-9 * (np.max(np.abs(od)) + 1e-300)
+    ef, et = force_err(g, o)
+    if precision == "fp64":
+        assert ef <= 1e-9
+    else:
+        # forces on the (slightly) diverged FP32 trajectory: no worse than
+        # those of the run searching every step
+        ef1, _ = force_err(g1, o)
+        assert ef <= 5 * ef1 + 1e-6, (ef, ef1)
+
+
+def test_dynamic_search_keeps_fast_particles_safe(Dem):
+    """A fast particle shortens the chunks between decisions; the displacement
+    guard (which would report a missed contact) never trips."""
+    sc = W.box_scene(n=300, L=0.03, seed=9)
+    sc["config"]["rebuild_interval"] = 0
+    rng = np.random.default_rng(3)
+    sc["particles"]["vel"] = rng.normal(0.0, 1.0, (300, 3))
+    g = Dem.from_scene(sc)
+    o = oracle_from_scene(dict(sc, config=dict(sc["config"], rebuild_interval=1)))
+    g.step(400)
+    o.step(400)
+    assert np.max(np.abs(g.get_state()["pos"] - o.state()["pos"])) <= 1e-6 * 3e-3
+    assert g.get_stats()["n_rebuilds"] > 10
