@@ -39,7 +39,8 @@ class _Config(C.Structure):
                 ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
                 ("neighbor_threshold", C.c_double), ("cell_factor", C.c_double),
                 ("rebuild_interval", C.c_int32), ("integrator", C.c_int32),
-                ("rolling_model", C.c_int32), ("pad", C.c_int32)]
+                ("rolling_model", C.c_int32), ("contact_model", C.c_int32),
+                ("characteristic_velocity", C.c_double)]
 
 
 class _Material(C.Structure):
@@ -115,7 +116,8 @@ class OracleSim:
 
     def __init__(self, dt, gravity=(0.0, 0.0, -9.81), domain_lo=(0, 0, 0),
                  domain_hi=(1, 1, 1), neighbor_threshold=1.3, cell_factor=None,
-                 rebuild_interval=20, integrator="verlet", rolling_model="constant"):
+                 rebuild_interval=20, integrator="verlet", rolling_model="constant",
+                 contact_model="nonlinear", characteristic_velocity=0.0):
         lib = _load()
         cfg = _Config()
         cfg.dt = dt
@@ -126,7 +128,9 @@ class OracleSim:
         cfg.cell_factor = neighbor_threshold if cell_factor is None else cell_factor
         cfg.rebuild_interval = rebuild_interval
         cfg.integrator = {"verlet": 0, "euler": 1}[integrator]
-        cfg.rolling_model = {"none": 0, "constant": 1}[rolling_model]
+        cfg.rolling_model = {"none": 0, "constant": 1, "viscous": 2}[rolling_model]
+        cfg.contact_model = {"nonlinear": 0, "linear": 1}[contact_model]
+        cfg.characteristic_velocity = characteristic_velocity
         self._lib = lib
         self._h = C.c_void_p()
         _check(lib.ora_create(C.byref(cfg), C.byref(self._h)), "ora_create")
@@ -266,7 +270,9 @@ def oracle_from_scene(scene: dict) -> OracleSim:
     sim = OracleSim(dt=c["dt"], gravity=c["gravity"], domain_lo=c["domain_lo"],
                     domain_hi=c["domain_hi"], neighbor_threshold=c["neighbor_threshold"],
                     cell_factor=c["cell_factor"], rebuild_interval=c["rebuild_interval"],
-                    integrator=c["integrator"], rolling_model=c["rolling_model"])
+                    integrator=c["integrator"], rolling_model=c["rolling_model"],
+                    contact_model=c.get("contact_model", "nonlinear"),
+                    characteristic_velocity=c.get("characteristic_velocity", 0.0))
     for t, m in enumerate(scene["materials"]):
         sim.set_material(t, m["density"], m["youngs"], m["poisson"], m["restitution"],
                          m["friction"], m["rolling_friction"])

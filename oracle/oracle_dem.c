@@ -17,7 +17,8 @@
  *   Sec. 2.1, Eqs. (nonlinearkn)-(nonlinearetat) and the table of effective
  *             parameters: Hertz-Mindlin coefficients
  *   Sec. 2.1, Eq. (torque_t)       tangential torque
- *   Sec. 2.1, table of rolling models, first row: constant rolling torque
+ *   Sec. 2.1, Eqs. (linearkn), (linearetan): linear spring-dashpot coefficients
+ *   Sec. 2.1, table of rolling models: constant and viscous rolling torque
  *   Sec. 2.1, Eqs. (coulomb_overlap)-(coulomb_overlap3): Coulomb limit with
  *             truncation of the tangential overlap
  *   Sec. 2.1, last paragraph       particle-wall contacts use the same law
@@ -49,7 +50,11 @@
  *     restitution, friction and rolling friction are the wall material's;
  *   - unlike particle types: restitution, friction and rolling friction are the
  *     arithmetic means of the two materials;
- *   - particles outside the domain box become inactive at a contact search.
+ *   - particles outside the domain box become inactive at a contact search;
+ *   - viscous rolling torque against a wall: V_omega = R_i (omega_i -
+ *     Omega_wall) x n (the particle's lever arm, spin relative to the wall's);
+ *   - linear model: the tangential spring and damping constants equal the
+ *     normal ones; e = 1 gives zero damping (the limit of the formula).
  */
 #include "oracle_dem.h"
 
@@ -137,23 +142,26 @@ static double beta_of(double e) {
   return le / sqrt(le * le + PI * PI);
 }
 
-/* Everything the Hertz-Mindlin law needs about a contact besides kinematics. */
+/* Everything the contact law needs about a contact besides kinematics. */
 typedef struct {
   double me, Re, Ye, Ge, e, mu, mur;
 } ora_contact_props;
 
 /*
- * The nonlinear (Hertz-Mindlin) contact law, Sec. 2.1, for one contact.
+ * The spring-dashpot contact law of Sec. 2.1 for one contact, with the
+ * nonlinear (Hertz-Mindlin) or the linear spring and damping constants.
  * Inputs: overlap dn > 0, unit normal n from body i towards body j, contact
  * relative velocity vij, relative angular velocity wrel = omega_i - omega_j,
- * the lever arms Ri, Rj and the tangential overlap (updated in place).
+ * the rolling velocity vroll (V_omega of the table of rolling models), the
+ * lever arms Ri, Rj and the tangential overlap (updated in place).
  * Outputs: the force on i (normal + tangential), the torques on i and j, and
  * |F^n + F^t| for the force scale.
  */
-static void hertz_mindlin(const ora_contact_props* cp, int rolling_model, double dt,
-                          double dn, const double* n, const double* vij,
-                          const double* wrel, double Ri, double Rj, double* delta_t,
-                          double* Fi, double* Mi, double* Mj, double* fmag) {
+static void contact_law(const ora_contact_props* cp, const ora_config* cfg, double dn,
+                        const double* n, const double* vij, const double* wrel,
+                        const double* vroll, double Ri, double Rj, double* delta_t,
+                        double* Fi, double* Mi, double* Mj, double* fmag) {
+  const double dt = cfg->dt;
   double vn = vdot(vij, n);
   double vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
   double vrt[3];
@@ -161,14 +169,31 @@ static void hertz_mindlin(const ora_contact_props* cp, int rolling_model, double
   /* Eq. (delta_t): single-step accumulation, before the force is evaluated */
   for (int k = 0; k < 3; ++k) delta_t[k] = delta_t[k] + vrt[k] * dt;
 
-  double beta = beta_of(cp->e);
-  double q = sqrt(cp->Re * dn);
-  double kn = 4.0 / 3.0 * cp->Ye * q;         /* Eq. (nonlinearkn) */
-  double kt = 8.0 * cp->Ge * q;               /* Eq. (nonlinearkt) */
-  double Sn = 2.0 * cp->Ye * q;               /* S_n */
-  double St = 8.0 * cp->Ge * q;               /* S_t */
-  double etan = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(Sn * cp->me); /* Eq. (nonlinearetan) */
-  double etat = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(St * cp->me); /* Eq. (nonlinearetat) */
+  double kn, kt, etan, etat;
+  if (cfg->contact_model == 0) {
+    double beta = beta_of(cp->e);
+    double q = sqrt(cp->Re * dn);
+    kn = 4.0 / 3.0 * cp->Ye * q;                /* Eq. (nonlinearkn) */
+    kt = 8.0 * cp->Ge * q;                      /* Eq. (nonlinearkt) */
+    double Sn = 2.0 * cp->Ye * q;               /* S_n */
+    double St = 8.0 * cp->Ge * q;               /* S_t */
+    etan = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(Sn * cp->me); /* Eq. (nonlinearetan) */
+    etat = -2.0 * sqrt(5.0 / 6.0) * beta * sqrt(St * cp->me); /* Eq. (nonlinearetat) */
+  } else {
+    /* linear model, Eqs. (linearkn), (linearetan); the tangential constants
+       are the same; e = 1 (ln e = 0) is the undamped limit */
+    double V = cfg->characteristic_velocity;
+    double sr = sqrt(cp->Re);
+    kn = 16.0 / 15.0 * sr * cp->Ye * pow(15.0 * cp->me * V * V / (16.0 * sr * cp->Ye), 0.2);
+    double le = log(cp->e);
+    etan = 0.0;
+    if (le != 0.0) {
+      double pl = PI / le;
+      etan = sqrt(4.0 * cp->me * kn / (1.0 + pl * pl));
+    }
+    kt = kn;
+    etat = etan;
+  }
 
   double Fn[3], Ft[3];
   for (int k = 0; k < 3; ++k) {
@@ -190,11 +215,18 @@ static void hertz_mindlin(const ora_contact_props* cp, int rolling_model, double
   double nxft[3];
   vcross(n, Ft, nxft);
   double Mr[3] = {0.0, 0.0, 0.0};
-  if (rolling_model == 1) {
+  if (cfg->rolling_model == 1) {
     /* constant rolling torque, first row of the rolling-model table */
     double wn = vnorm(wrel);
     if (wn > 0.0) {
       for (int k = 0; k < 3; ++k) Mr[k] = -cp->mur * cp->Re * fn * (wrel[k] / wn);
+    }
+  } else if (cfg->rolling_model == 2) {
+    /* viscous rolling torque, second row: scaled by |V_omega| */
+    double wn = vnorm(wrel);
+    double vr = vnorm(vroll);
+    if (wn > 0.0) {
+      for (int k = 0; k < 3; ++k) Mr[k] = -cp->mur * cp->Re * fn * vr * (wrel[k] / wn);
     }
   }
   double Fsum[3];
@@ -257,8 +289,8 @@ static int pp_contact(const ora_sim* s, const double* xi, const double* xj,
   }
   ora_contact_props cp;
   pp_props(s, ti, tj, mi, mj, Ri, Rj, &cp);
-  hertz_mindlin(&cp, s->cfg.rolling_model, s->cfg.dt, dn, n, vij, wrel, Ri, Rj, delta_t,
-                Fi, Mi, Mj, fmag);
+  /* V_omega = omega_i x R_i n_ij - omega_j x R_j n_ji = (R_i w_i + R_j w_j) x n */
+  contact_law(&cp, &s->cfg, dn, n, vij, wrel, rwxn, Ri, Rj, delta_t, Fi, Mi, Mj, fmag);
   return 1;
 }
 
@@ -368,9 +400,13 @@ static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const doubl
   cp.e = b->restitution;
   cp.mu = b->friction;
   cp.mur = b->rolling_friction;
+  /* V_omega against a wall: the particle's lever arm with the spin relative
+     to the wall's, R (omega - Omega_wall) x n */
+  double rrel[3] = {R * wrel[0], R * wrel[1], R * wrel[2]};
+  double vroll[3];
+  vcross(rrel, g.n, vroll);
   double Mj[3];
-  hertz_mindlin(&cp, s->cfg.rolling_model, s->cfg.dt, dn, g.n, vij, wrel, R, 0.0, delta_t,
-                Fi, Mi, Mj, fmag);
+  contact_law(&cp, &s->cfg, dn, g.n, vij, wrel, vroll, R, 0.0, delta_t, Fi, Mi, Mj, fmag);
   return 1;
 }
 
@@ -677,8 +713,10 @@ static int one_step(ora_sim* s) {
 int ora_create(const ora_config* cfg, ora_sim** out) {
   if (!cfg || !out) return ORA_EINVAL;
   if (!(cfg->dt > 0.0) || cfg->rebuild_interval < 1 || cfg->integrator < 0 ||
-      cfg->integrator > 1 || cfg->rolling_model < 0 || cfg->rolling_model > 1)
+      cfg->integrator > 1 || cfg->rolling_model < 0 || cfg->rolling_model > 2 ||
+      cfg->contact_model < 0 || cfg->contact_model > 1)
     return ORA_EINVAL;
+  if (cfg->contact_model == 1 && !(cfg->characteristic_velocity > 0.0)) return ORA_EINVAL;
   if (!(cfg->neighbor_threshold >= 1.0)) return ORA_EINVAL;
   if (!(cfg->cell_factor >= 1.0)) return ORA_EINVAL;
   for (int k = 0; k < 3; ++k)

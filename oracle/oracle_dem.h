@@ -40,8 +40,9 @@ typedef struct {
   double cell_factor;        /* h / d_max, >= neighbor_threshold if given  */
   int32_t rebuild_interval;  /* contact search every K steps ("constant")  */
   int32_t integrator;        /* 0 velocity Verlet, 1 explicit Euler        */
-  int32_t rolling_model;     /* 0 none, 1 constant torque                  */
-  int32_t pad;
+  int32_t rolling_model;     /* 0 none, 1 constant torque, 2 viscous torque */
+  int32_t contact_model;     /* 0 nonlinear (Hertz-Mindlin), 1 linear      */
+  double characteristic_velocity; /* V of the linear model [m/s]           */
 } ora_config;
 
 typedef struct {
