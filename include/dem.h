@@ -78,7 +78,8 @@ typedef struct {
                                 r_s - d_max since the last search */
   int32_t integrator;        /* 0 velocity Verlet (Eqs. halfstep/newvv),
                                 1 explicit Euler (Eq. integ_EE) */
-  int32_t rolling_model;     /* 0 none, 1 constant torque (Sec. 2.1 table) */
+  int32_t rolling_model;     /* 0 none, 1 constant torque, 2 viscous torque
+                                (Sec. 2.1, table of rolling models) */
   int32_t precision;         /* 0 plain FP64; 1 contact law in FP32 with
                                 positions, velocities, tangential history and
                                 force sums in FP64 */
@@ -88,6 +89,13 @@ typedef struct {
   void* hip_stream;          /* optional hipStream_t the library orders its
                                 work after (and that waits for the library);
                                 NULL = none */
+  int32_t contact_model;     /* 0 nonlinear Hertz-Mindlin (Eqs. nonlinearkn-
+                                nonlinearetat), 1 linear spring-dashpot (Eqs.
+                                linearkn, linearetan; tangential constants
+                                equal to the normal ones) */
+  int32_t reserved;          /* must be 0 */
+  double characteristic_velocity; /* V of Eq. (linearkn) [m/s], > 0 for the
+                                     linear model, ignored otherwise */
 } dem_config;
 
 typedef struct {

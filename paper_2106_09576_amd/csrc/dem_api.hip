@@ -224,14 +224,25 @@ double damping_factor(double e) {
   return -2.0 * sqrt(5.0 / 6.0) * beta;
 }
 
-PairCoef make_coef(double Ye, double Ge, double e, double mu, double mur) {
+PairCoef make_coef(const dem_config& cfg, double Ye, double Ge, double e, double mu,
+                   double mur) {
   PairCoef q;
   memset(&q, 0, sizeof(q));
-  const double ceta = damping_factor(e);
-  q.kn = 4.0 / 3.0 * Ye;
-  q.kt = 8.0 * Ge;
-  q.en = ceta * sqrt(2.0 * Ye);
-  q.et = ceta * sqrt(8.0 * Ge);
+  if (cfg.contact_model == 0) {
+    const double ceta = damping_factor(e);
+    q.kn = 4.0 / 3.0 * Ye;
+    q.kt = 8.0 * Ge;
+    q.en = ceta * sqrt(2.0 * Ye);
+    q.et = ceta * sqrt(8.0 * Ge);
+  } else {
+    // linear model: k = kn (R_e^2 m_e)^(1/5), eta = en sqrt(m_e k)
+    const double V = cfg.characteristic_velocity;
+    q.kn = 16.0 / 15.0 * Ye * pow(15.0 * V * V / (16.0 * Ye), 0.2);
+    q.kt = q.kn;
+    const double le = log(e);
+    q.en = le == 0.0 ? 0.0 : 2.0 / sqrt(1.0 + (kPi / le) * (kPi / le));
+    q.et = q.en;
+  }
   q.mu = mu;
   q.mur = mur;
   return q;
@@ -712,6 +723,7 @@ int commit(dem_ctx* c) {
   sp.n = (int)N;
   sp.max_nb = max_nb;
   sp.rolling = c->cfg.rolling_model;
+  sp.model = c->cfg.contact_model;
   sp.n_keys = (uint32_t)total_keys;
   sp.drift_scale = ihs_min == ihs_max ? c->cfg.dt * ihs_max : 0.0;
 
@@ -818,9 +830,9 @@ int commit(dem_ctx* c) {
         const double mur =
             ta == tb ? A.rolling_friction : 0.5 * (A.rolling_friction + M.rolling_friction);
         const size_t idx = (size_t)D.coef_base + (size_t)ta * kMaxTypes + (size_t)tb;
-        pp[idx] = make_coef(Ye, Ge, e, mu, mur);
+        pp[idx] = make_coef(c->cfg, Ye, Ge, e, mu, mur);
         // particle type ta against wall material tb: the wall's e, mu, mu_r
-        pw[idx] = make_coef(Ye, Ge, M.restitution, M.friction, M.rolling_friction);
+        pw[idx] = make_coef(c->cfg, Ye, Ge, M.restitution, M.friction, M.rolling_friction);
       }
   }
 
@@ -912,8 +924,13 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
   if (!(cfg->cell_factor >= 1.0)) return set_err(DEM_EINVAL, "cell_factor must be >= 1");
   if (cfg->integrator < 0 || cfg->integrator > 1)
     return set_err(DEM_EINVAL, "integrator must be 0 (Verlet) or 1 (Euler)");
-  if (cfg->rolling_model < 0 || cfg->rolling_model > 1)
-    return set_err(DEM_EINVAL, "rolling_model must be 0 or 1");
+  if (cfg->rolling_model < 0 || cfg->rolling_model > 2)
+    return set_err(DEM_EINVAL, "rolling_model must be 0 (none), 1 (constant) or 2 (viscous)");
+  if (cfg->contact_model < 0 || cfg->contact_model > 1)
+    return set_err(DEM_EINVAL, "contact_model must be 0 (nonlinear) or 1 (linear)");
+  if (cfg->contact_model == 1 &&
+      !(cfg->characteristic_velocity > 0.0 && std::isfinite(cfg->characteristic_velocity)))
+    return set_err(DEM_EINVAL, "the linear model needs characteristic_velocity > 0");
   if (cfg->precision < 0 || cfg->precision > 1)
     return set_err(DEM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 law)");
   if (cfg->n_instances < 1 || cfg->n_instances > kMaxInstances)

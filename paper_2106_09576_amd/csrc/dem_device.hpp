@@ -32,6 +32,9 @@ enum : int {
 // en = -2 sqrt(5/6) beta sqrt(2 Y_e), et = -2 sqrt(5/6) beta sqrt(8 G_e),
 // so that k_n = kn q, k_t = kt q, eta_n = en sqrt(m_e q), eta_t = et sqrt(m_e q)
 // with q = sqrt(R_e delta_n); mu and mur are the friction coefficients.
+// Linear model: kn = kt = (16/15) Y_e (15 V^2 / (16 Y_e))^(1/5) and en = et =
+// 2 / sqrt(1 + (pi / ln e)^2), so that k = kn (R_e^2 m_e)^(1/5) and eta = en
+// sqrt(m_e k) (Eqs. linearkn, linearetan).
 struct PairCoef {
   double kn, kt, en, et, mu, mur, pad0, pad1;
 };
@@ -82,7 +85,8 @@ struct StepParams {
   double g[3];
   int n;           // number of particles of all instances (active + inactive)
   int max_nb;      // neighbour slots per particle
-  int rolling;     // 0 none, 1 constant torque
+  int rolling;     // 0 none, 1 constant torque, 2 viscous torque
+  int model;       // 0 nonlinear (Hertz-Mindlin), 1 linear spring-dashpot
   uint32_t n_keys; // total cell keys; key n_keys collects inactive particles
   double drift_scale;  // dt * 2 / skin when every instance has the same skin,
                        // else 0 (then taken per particle from its instance)

@@ -532,6 +532,7 @@ struct Fast<double> {
   static __device__ __forceinline__ double sqrt(double x) {
     return x > 0.0 ? x * rsqrt(x) : 0.0;
   }
+  static __device__ __forceinline__ double root5(double x) { return ::pow(x, 0.2); }
 };
 
 template <>
@@ -539,21 +540,28 @@ struct Fast<float> {
   static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float root5(float x) { return ::powf(x, 0.2f); }
 };
 
-// The Hertz-Mindlin law (Sec. 2.1) in arithmetic type R for one contact, given
-// the overlap dn >= 0, the unit normal n from body i to body j, the contact
-// relative velocity vij, wrel = omega_i - omega_j, the effective mass and
-// radius and the lever arm Ri.  The tangential overlap dtl stays in FP64 and
-// is updated in place (Eq. delta_t before the force, Coulomb truncation of
-// Eqs. coulomb_overlap..3 after it).  Output: force and torque on body i.
-// With k_n = (4/3) Y_e q, k_t = 8 G_e q, eta = -2 sqrt(5/6) beta sqrt(S m_e),
-// q = sqrt(R_e dn), the per-pair constants are c.kn = 4/3 Y_e, c.kt = 8 G_e,
-// c.en = -2 sqrt(5/6) beta sqrt(2 Y_e), c.et = -2 sqrt(5/6) beta sqrt(8 G_e).
+// The spring-dashpot law (Sec. 2.1) in arithmetic type R for one contact,
+// given the overlap dn >= 0, the unit normal n from body i to body j, the
+// contact relative velocity vij, wrel = omega_i - omega_j, the rolling
+// velocity vroll (V_omega of the table of rolling models), the effective mass
+// and radius and the lever arm Ri.  The tangential overlap dtl stays in FP64
+// and is updated in place (Eq. delta_t before the force, Coulomb truncation
+// of Eqs. coulomb_overlap..3 after it).  Output: force and torque on body i.
+// model 0, Hertz-Mindlin: k_n = (4/3) Y_e q, k_t = 8 G_e q, eta = -2 sqrt(5/6)
+// beta sqrt(S m_e), q = sqrt(R_e dn); the per-pair constants are c.kn = 4/3
+// Y_e, c.kt = 8 G_e, c.en = -2 sqrt(5/6) beta sqrt(2 Y_e), c.et = -2 sqrt(5/6)
+// beta sqrt(8 G_e).  model 1, linear (Eqs. linearkn, linearetan, the same
+// constants tangentially): k = c.kn (R_e^2 m_e)^(1/5) with c.kn = (16/15) Y_e
+// (15 V^2 / (16 Y_e))^(1/5), eta = c.en sqrt(m_e k) with c.en = 2 / sqrt(1 +
+// (pi / ln e)^2).
 template <typename R>
-__device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, double dt, R dn,
-                                       const R n[3], const R vij[3], const R wrel[3], R me,
-                                       R Re, R Ri, double dtl[3], double Fi[3], double Mi[3]) {
+__device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, int model, double dt,
+                                       R dn, const R n[3], const R vij[3], const R wrel[3],
+                                       const R vroll[3], R me, R Re, R Ri, double dtl[3],
+                                       double Fi[3], double Mi[3]) {
   using M = Fast<R>;
   const R vn = (vij[0] * n[0] + vij[1] * n[1]) + vij[2] * n[2];
   const R vrn[3] = {vn * n[0], vn * n[1], vn * n[2]};
@@ -561,12 +569,20 @@ __device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, double dt
   dtl[0] = dtl[0] + (double)vrt[0] * dt;
   dtl[1] = dtl[1] + (double)vrt[1] * dt;
   dtl[2] = dtl[2] + (double)vrt[2] * dt;
-  const R q = M::sqrt(Re * dn);
-  const R kn = (R)c.kn * q;
-  const R kt = (R)c.kt * q;
-  const R sq = M::sqrt(me * q);
-  const R etan = (R)c.en * sq;
-  const R etat = (R)c.et * sq;
+  R kn, kt, etan, etat;
+  if (model == 0) {
+    const R q = M::sqrt(Re * dn);
+    kn = (R)c.kn * q;
+    kt = (R)c.kt * q;
+    const R sq = M::sqrt(me * q);
+    etan = (R)c.en * sq;
+    etat = (R)c.et * sq;
+  } else {
+    kn = (R)c.kn * M::root5((Re * Re) * me);
+    kt = kn;
+    etan = (R)c.en * M::sqrt(me * kn);
+    etat = etan;
+  }
   const R knd = kn * dn;
   R Fn[3], Ft[3];
 #pragma unroll
@@ -589,10 +605,13 @@ __device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, double dt
     }
   }
   R Mr[3] = {(R)0, (R)0, (R)0};
-  if (rolling == 1) {
+  if (rolling != 0) {
     const R wn2 = (wrel[0] * wrel[0] + wrel[1] * wrel[1]) + wrel[2] * wrel[2];
     if (wn2 > (R)0) {
-      const R sc = -((R)c.mur * Re * fn) * M::rsqrt(wn2);
+      R mag = (R)c.mur * Re * fn;  // constant torque; viscous: times |V_omega|
+      if (rolling == 2)
+        mag = mag * M::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2]);
+      const R sc = -mag * M::rsqrt(wn2);
       Mr[0] = sc * wrel[0];
       Mr[1] = sc * wrel[1];
       Mr[2] = sc * wrel[2];
@@ -612,13 +631,14 @@ __device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, double dt
 // evaluation from j's side gives exactly -F and -delta_t: every symmetric
 // quantity is formed from commutative operations of the two particles' data.
 template <typename R>
-__device__ __forceinline__ void pp_contact(const PairCoef& c, int rolling, double dt,
+__device__ __forceinline__ void pp_contact(const PairCoef& c, int rolling, int model, double dt,
                                            double4 xi, double4 vi, double4 wi, double4 xj,
                                            double4 vj, double4 wj, double dtl[3], double Fi[3],
                                            double Mi[3]);
 
 template <>
-__device__ __forceinline__ void pp_contact<double>(const PairCoef& c, int rolling, double dt,
+__device__ __forceinline__ void pp_contact<double>(const PairCoef& c, int rolling, int model,
+                                                   double dt,
                                                    double4 xi, double4 vi, double4 wi,
                                                    double4 xj, double4 vj, double4 wj,
                                                    double dtl[3], double Fi[3], double Mi[3]) {
@@ -632,19 +652,22 @@ __device__ __forceinline__ void pp_contact<double>(const PairCoef& c, int rollin
   if (dn < 0.0) dn = 0.0;
   const double n[3] = {dx[0] * inv_d, dx[1] * inv_d, dx[2] * inv_d};
   const double rw[3] = {Ri * wi.x + Rj * wj.x, Ri * wi.y + Rj * wj.y, Ri * wi.z + Rj * wj.z};
-  const double vij[3] = {(vi.x - vj.x) + (rw[1] * n[2] - rw[2] * n[1]),
-                         (vi.y - vj.y) + (rw[2] * n[0] - rw[0] * n[2]),
-                         (vi.z - vj.z) + (rw[0] * n[1] - rw[1] * n[0])};
+  // rolling velocity V_omega = (R_i w_i + R_j w_j) x n, part of the contact velocity
+  const double vroll[3] = {rw[1] * n[2] - rw[2] * n[1], rw[2] * n[0] - rw[0] * n[2],
+                           rw[0] * n[1] - rw[1] * n[0]};
+  const double vij[3] = {(vi.x - vj.x) + vroll[0], (vi.y - vj.y) + vroll[1],
+                         (vi.z - vj.z) + vroll[2]};
   const double wrel[3] = {wi.x - wj.x, wi.y - wj.y, wi.z - wj.z};
   const double me = M::rcp(vi.w + vj.w);
   const double Re = (Ri * Rj) * M::rcp(rsum);
-  hm_law<double>(c, rolling, dt, dn, n, vij, wrel, me, Re, Ri, dtl, Fi, Mi);
+  hm_law<double>(c, rolling, model, dt, dn, n, vij, wrel, vroll, me, Re, Ri, dtl, Fi, Mi);
 }
 
 // FP32 contact law.  The overlap is formed without cancellation:
 // dn = (rsum^2 - d^2) / (rsum + d) with the numerator from FP64 positions.
 template <>
-__device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling, double dt,
+__device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling, int model,
+                                                  double dt,
                                                   double4 xi, double4 vi, double4 wi,
                                                   double4 xj, double4 vj, double4 wj,
                                                   double dtl[3], double Fi[3], double Mi[3]) {
@@ -661,19 +684,20 @@ __device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling
   const float Ri = (float)xi.w, Rj = (float)xj.w;
   const float rw[3] = {Ri * (float)wi.x + Rj * (float)wj.x, Ri * (float)wi.y + Rj * (float)wj.y,
                        Ri * (float)wi.z + Rj * (float)wj.z};
-  const float vij[3] = {(float)(vi.x - vj.x) + (rw[1] * n[2] - rw[2] * n[1]),
-                        (float)(vi.y - vj.y) + (rw[2] * n[0] - rw[0] * n[2]),
-                        (float)(vi.z - vj.z) + (rw[0] * n[1] - rw[1] * n[0])};
+  const float vroll[3] = {rw[1] * n[2] - rw[2] * n[1], rw[2] * n[0] - rw[0] * n[2],
+                          rw[0] * n[1] - rw[1] * n[0]};
+  const float vij[3] = {(float)(vi.x - vj.x) + vroll[0], (float)(vi.y - vj.y) + vroll[1],
+                        (float)(vi.z - vj.z) + vroll[2]};
   const float wrel[3] = {(float)(wi.x - wj.x), (float)(wi.y - wj.y), (float)(wi.z - wj.z)};
   const float me = M::rcp((float)(vi.w + vj.w));
   const float Re = (Ri * Rj) * M::rcp(Ri + Rj);
-  hm_law<float>(c, rolling, dt, dn, n, vij, wrel, me, Re, Ri, dtl, Fi, Mi);
+  hm_law<float>(c, rolling, model, dt, dn, n, vij, wrel, vroll, me, Re, Ri, dtl, Fi, Mi);
 }
 
 // Particle against wall W, the wall acting as a body of infinite mass and
 // radius whose contact point moves with the wall's surface velocity.
 template <typename R>
-__device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, double dt,
+__device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int model, double dt,
                                            const WallDev& W, double skin, double4 xi,
                                            double4 vi, double4 wi, double dtl[3],
                                            double Fi[3], double Mi[3]) {
@@ -700,8 +724,12 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, doubl
   const R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
   const R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
   const R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
+  // rolling velocity against a wall: R_i (omega_i - Omega_wall) x n
+  const R rr[3] = {(R)Ri * wrel[0], (R)Ri * wrel[1], (R)Ri * wrel[2]};
+  const R vroll[3] = {rr[1] * n[2] - rr[2] * n[1], rr[2] * n[0] - rr[0] * n[2],
+                      rr[0] * n[1] - rr[1] * n[0]};
   const R me = Fast<R>::rcp((R)vi.w);
-  hm_law<R>(c, rolling, dt, (R)dn, n, vij, wrel, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
+  hm_law<R>(c, rolling, model, dt, (R)dn, n, vij, wrel, vroll, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
 }
 
 // ------------------------------------------------------------------- force
@@ -786,7 +814,7 @@ __device__ __forceinline__ double force_particle(
         dtl[2] = l.hist[2 * cap + e];
       }
       double Fi[3], Mi[3];
-      pp_contact<R>(ppi[tj], sp.rolling, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      pp_contact<R>(ppi[tj], sp.rolling, sp.model, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       l.hist[e] = dtl[0];
       l.hist[cap + e] = dtl[1];
       l.hist[2 * cap + e] = dtl[2];
@@ -814,7 +842,7 @@ __device__ __forceinline__ double force_particle(
                      ws.hist[(int64_t)(3 * s + 2) * n + i]};
     double Fi[3], Mi[3];
     if (t >= W.t_on && t < W.t_off) {
-      pw_contact<R>(pwi[W.material], sp.rolling, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
+      pw_contact<R>(pwi[W.material], sp.rolling, sp.model, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
     } else {
       dtl[0] = dtl[1] = dtl[2] = 0.0;
       Fi[0] = Fi[1] = Fi[2] = 0.0;

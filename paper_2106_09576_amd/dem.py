@@ -40,7 +40,8 @@ class dem_config(C.Structure):
                 ("rebuild_interval", C.c_int32), ("integrator", C.c_int32),
                 ("rolling_model", C.c_int32), ("precision", C.c_int32),
                 ("n_instances", C.c_int32), ("max_neighbors", C.c_int32),
-                ("hip_stream", C.c_void_p)]
+                ("hip_stream", C.c_void_p), ("contact_model", C.c_int32),
+                ("reserved", C.c_int32), ("characteristic_velocity", C.c_double)]
 
 
 class dem_stats(C.Structure):
@@ -131,7 +132,8 @@ class Dem:
     def __init__(self, dt, gravity=(0.0, 0.0, -9.81), domain_lo=(0, 0, 0), domain_hi=(1, 1, 1),
                  neighbor_threshold=1.3, cell_factor=None, rebuild_interval=20,
                  integrator="verlet", rolling_model="constant", precision="fp64",
-                 max_neighbors=0, hip_stream=None, n_instances=1):
+                 max_neighbors=0, hip_stream=None, n_instances=1, contact_model="nonlinear",
+                 characteristic_velocity=0.0):
         self._lib = load_library()
         cfg = dem_config()
         cfg.dt = dt
@@ -142,7 +144,9 @@ class Dem:
         cfg.cell_factor = neighbor_threshold if cell_factor is None else cell_factor
         cfg.rebuild_interval = rebuild_interval
         cfg.integrator = {"verlet": 0, "euler": 1}[integrator]
-        cfg.rolling_model = {"none": 0, "constant": 1}[rolling_model]
+        cfg.rolling_model = {"none": 0, "constant": 1, "viscous": 2}[rolling_model]
+        cfg.contact_model = {"nonlinear": 0, "linear": 1}[contact_model]
+        cfg.characteristic_velocity = characteristic_velocity
         cfg.precision = {"fp64": 0, "fp32": 1}[precision]
         cfg.n_instances = n_instances
         cfg.max_neighbors = max_neighbors
@@ -336,7 +340,8 @@ class Dem:
                   cell_factor=c["cell_factor"], rebuild_interval=c["rebuild_interval"],
                   integrator=c["integrator"], rolling_model=c["rolling_model"],
                   precision=precision, max_neighbors=max_neighbors, hip_stream=hip_stream,
-                  n_instances=len(scenes))
+                  n_instances=len(scenes), contact_model=c.get("contact_model", "nonlinear"),
+                  characteristic_velocity=c.get("characteristic_velocity", 0.0))
         for k, s in enumerate(scenes):
             sim._add_scene(s, k, own_domain=len(scenes) > 1)
         if len(scenes) > 1:

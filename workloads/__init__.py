@@ -10,7 +10,8 @@ Scene dictionary layout::
 
     {"name": str,
      "config": {dt, gravity, domain_lo, domain_hi, neighbor_threshold,
-                cell_factor, rebuild_interval, integrator, rolling_model},
+                cell_factor, rebuild_interval, integrator, rolling_model,
+                contact_model, characteristic_velocity},
      "materials": [dict(density, youngs, poisson, restitution, friction,
                         rolling_friction), ...],        # index = type id
      "walls": [dict(kind="plane", point, normal, material, extent=None,
@@ -33,12 +34,13 @@ BOX_MATERIAL = dict(density=2500.0, youngs=1.0e6, poisson=0.3, restitution=0.9,
 
 
 def _cfg(dt, lo, hi, threshold=1.3, cell_factor=None, K=20, integrator="verlet",
-         rolling="constant", gravity=(0.0, 0.0, -9.81)):
+         rolling="constant", gravity=(0.0, 0.0, -9.81), model="nonlinear", V=0.0):
     return dict(dt=float(dt), gravity=tuple(float(g) for g in gravity),
                 domain_lo=tuple(float(v) for v in lo), domain_hi=tuple(float(v) for v in hi),
                 neighbor_threshold=float(threshold),
                 cell_factor=float(threshold if cell_factor is None else cell_factor),
-                rebuild_interval=int(K), integrator=integrator, rolling_model=rolling)
+                rebuild_interval=int(K), integrator=integrator, rolling_model=rolling,
+                contact_model=model, characteristic_velocity=float(V))
 
 
 def _particles(pos, radius, vel=None, omega=None, types=None):
@@ -200,6 +202,7 @@ def drum_scene(n=1_000_000, d=3.0e-3, R_drum=None, L=None, omega=1.0, seed=2,
 def dense_snapshot(n=3000, d=3.0e-3, seed=7, overlap=0.01, vmax=0.05, wmax=20.0,
                    polydisperse=0.0, n_types=1, dt=1.0e-5, K=5, walls=True,
                    rolling="constant", integrator="verlet", friction=None,
+                   model="nonlinear", V=0.0,
                    threshold=1.3):
     """A jammed-like random snapshot that exercises every branch of the law:
     jittered lattice with spacing slightly below d (so many pairs overlap),
@@ -236,7 +239,8 @@ def dense_snapshot(n=3000, d=3.0e-3, seed=7, overlap=0.01, vmax=0.05, wmax=20.0,
     lo = (0.0, 0.0, 0.0)
     hi = tuple(hi_box + d)
     return dict(name=f"dense_{n}", config=_cfg(dt, lo, hi, threshold=threshold, K=K,
-                                                 rolling=rolling, integrator=integrator),
+                                                 rolling=rolling, integrator=integrator,
+                                                 model=model, V=V),
                 materials=mats, walls=wl,
                 particles=_particles(pts, radius, vel, om, types))
 
