@@ -545,8 +545,8 @@ struct Fast<float> {
 
 // The spring-dashpot law (Sec. 2.1) in arithmetic type R for one contact,
 // given the overlap dn >= 0, the unit normal n from body i to body j, the
-// contact relative velocity vij, wrel = omega_i - omega_j, the rolling
-// velocity vroll (V_omega of the table of rolling models), the effective mass
+// contact relative velocity vij, wrel = omega_i - omega_j, the rolling speed
+// vr = |V_omega| (table of rolling models; used by the viscous model), the effective mass
 // and radius and the lever arm Ri.  The tangential overlap dtl stays in FP64
 // and is updated in place (Eq. delta_t before the force, Coulomb truncation
 // of Eqs. coulomb_overlap..3 after it).  Output: force and torque on body i.
@@ -560,7 +560,7 @@ struct Fast<float> {
 template <typename R>
 __device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, int model, double dt,
                                        R dn, const R n[3], const R vij[3], const R wrel[3],
-                                       const R vroll[3], R me, R Re, R Ri, double dtl[3],
+                                       R vr, R me, R Re, R Ri, double dtl[3],
                                        double Fi[3], double Mi[3]) {
   using M = Fast<R>;
   const R vn = (vij[0] * n[0] + vij[1] * n[1]) + vij[2] * n[2];
@@ -609,8 +609,7 @@ __device__ __forceinline__ void hm_law(const PairCoef& c, int rolling, int model
     const R wn2 = (wrel[0] * wrel[0] + wrel[1] * wrel[1]) + wrel[2] * wrel[2];
     if (wn2 > (R)0) {
       R mag = (R)c.mur * Re * fn;  // constant torque; viscous: times |V_omega|
-      if (rolling == 2)
-        mag = mag * M::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2]);
+      if (rolling == 2) mag = mag * vr;
       const R sc = -mag * M::rsqrt(wn2);
       Mr[0] = sc * wrel[0];
       Mr[1] = sc * wrel[1];
@@ -660,7 +659,8 @@ __device__ __forceinline__ void pp_contact<double>(const PairCoef& c, int rollin
   const double wrel[3] = {wi.x - wj.x, wi.y - wj.y, wi.z - wj.z};
   const double me = M::rcp(vi.w + vj.w);
   const double Re = (Ri * Rj) * M::rcp(rsum);
-  hm_law<double>(c, rolling, model, dt, dn, n, vij, wrel, vroll, me, Re, Ri, dtl, Fi, Mi);
+  const double vr = rolling == 2 ? M::sqrt(dot3(vroll, vroll)) : 0.0;
+  hm_law<double>(c, rolling, model, dt, dn, n, vij, wrel, vr, me, Re, Ri, dtl, Fi, Mi);
 }
 
 // FP32 contact law.  The overlap is formed without cancellation:
@@ -691,7 +691,10 @@ __device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling
   const float wrel[3] = {(float)(wi.x - wj.x), (float)(wi.y - wj.y), (float)(wi.z - wj.z)};
   const float me = M::rcp((float)(vi.w + vj.w));
   const float Re = (Ri * Rj) * M::rcp(Ri + Rj);
-  hm_law<float>(c, rolling, model, dt, dn, n, vij, wrel, vroll, me, Re, Ri, dtl, Fi, Mi);
+  const float vr =
+      rolling == 2 ? M::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2])
+                   : 0.0f;
+  hm_law<float>(c, rolling, model, dt, dn, n, vij, wrel, vr, me, Re, Ri, dtl, Fi, Mi);
 }
 
 // Particle against wall W, the wall acting as a body of infinite mass and
@@ -724,12 +727,16 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
   const R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
   const R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
   const R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
-  // rolling velocity against a wall: R_i (omega_i - Omega_wall) x n
-  const R rr[3] = {(R)Ri * wrel[0], (R)Ri * wrel[1], (R)Ri * wrel[2]};
-  const R vroll[3] = {rr[1] * n[2] - rr[2] * n[1], rr[2] * n[0] - rr[0] * n[2],
-                      rr[0] * n[1] - rr[1] * n[0]};
+  // rolling speed against a wall: |R_i (omega_i - Omega_wall) x n|
+  R vr = (R)0;
+  if (rolling == 2) {
+    const R rr[3] = {(R)Ri * wrel[0], (R)Ri * wrel[1], (R)Ri * wrel[2]};
+    const R vroll[3] = {rr[1] * n[2] - rr[2] * n[1], rr[2] * n[0] - rr[0] * n[2],
+                        rr[0] * n[1] - rr[1] * n[0]};
+    vr = Fast<R>::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2]);
+  }
   const R me = Fast<R>::rcp((R)vi.w);
-  hm_law<R>(c, rolling, model, dt, (R)dn, n, vij, wrel, vroll, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
+  hm_law<R>(c, rolling, model, dt, (R)dn, n, vij, wrel, vr, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
 }
 
 // ------------------------------------------------------------------- force
@@ -742,6 +749,51 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
 
 constexpr int kTouchedBit = (int)0x80000000u;
 constexpr int kIndexMask = 0x7fffffff;
+
+// The states of a window of consecutive sorted particles, staged in LDS by
+// the block that covers the middle of the window: in spatial (Morton) order
+// most neighbours of a block's particles lie inside it, and they are then
+// read from LDS instead of through the cache hierarchy.
+#ifndef DEM_TILE_HALO
+#define DEM_TILE_HALO 0
+#endif
+constexpr int kTileHalo = DEM_TILE_HALO;
+constexpr int kTileSize = kBlock + 2 * kTileHalo;
+
+struct Tile {
+  double4 p[kTileSize], v[kTileSize], w[kTileSize];
+  int in[kTileSize];
+  int lo, hi;  // staged particles [lo, hi)
+
+  __device__ __forceinline__ void stage(const ParticleBufs& src, const int* __restrict__ info,
+                                        int first, int n) {
+    const int a = first < 0 ? 0 : first;
+    const int b = first + kTileSize < n ? first + kTileSize : n;
+    for (int t = threadIdx.x; t < b - a; t += kBlock) {
+      p[t] = src.pos[a + t];
+      v[t] = src.vel[a + t];
+      w[t] = src.omg[a + t];
+      in[t] = info[a + t];
+    }
+    if (threadIdx.x == 0) {
+      lo = a;
+      hi = b > a ? b : a;
+    }
+  }
+  __device__ __forceinline__ bool has(int j) const { return j >= lo && j < hi; }
+  __device__ __forceinline__ double4 pos(const ParticleBufs& g, int j) const {
+    return has(j) ? p[j - lo] : g.pos[j];
+  }
+  __device__ __forceinline__ double4 vel(const ParticleBufs& g, int j) const {
+    return has(j) ? v[j - lo] : g.vel[j];
+  }
+  __device__ __forceinline__ double4 omg(const ParticleBufs& g, int j) const {
+    return has(j) ? w[j - lo] : g.omg[j];
+  }
+  __device__ __forceinline__ int info(const int* __restrict__ g, int j) const {
+    return has(j) ? in[j - lo] : g[j];
+  }
+};
 
 // Square of a step's drift |v| dt in units of half the skin: scale = dt * 2 /
 // skin.  Maxima of squares are taken on the device, the root on the host.
@@ -759,19 +811,19 @@ __device__ __forceinline__ double drift_scale(const StepParams& sp,
 // Forces on particle i and its integration; returns the squared drift of
 // this step in units of half the instance's skin (for the dynamic search
 // trigger) when asked for it.
-template <typename R, int MODE>
+template <typename R, int MODE, int MODEL>
 __device__ __forceinline__ double force_particle(
     const int i, const StepParams& sp, const InstDev* __restrict__ inst,
     const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
     const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
     const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
     double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
-    const int* __restrict__ flags, const bool want_drift) {
+    const int* __restrict__ flags, const bool want_drift, const Tile& tile) {
   const int n = sp.n;
-  double4 xi = in.pos[i];
-  double4 vi = in.vel[i];
-  double4 wi = in.omg[i];
-  const int inf = info[i];
+  double4 xi = tile.pos(in, i);
+  double4 vi = tile.vel(in, i);
+  double4 wi = tile.omg(in, i);
+  const int inf = tile.info(info, i);
   // frozen after an error, and for inactive particles: carry the state over
   if ((inf & kInactive) || *flags != 0) {
     out.pos[i] = xi;
@@ -799,14 +851,14 @@ __device__ __forceinline__ double force_particle(
     const int64_t e = nbr_entry(i, k, max_nb);
     const int jr = l.nbr[e];
     const int j = jr & kIndexMask;
-    const double4 xj = in.pos[j];
+    const double4 xj = tile.pos(in, j);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
     const double d2 = (dx * dx + dy * dy) + dz * dz;
     const double rsum = xi.w + xj.w;
     if (d2 < rsum * rsum) {
-      const double4 vj = in.vel[j];
-      const double4 wj = in.omg[j];
-      const int tj = info[j] & kTypeMask;
+      const double4 vj = tile.vel(in, j);
+      const double4 wj = tile.omg(in, j);
+      const int tj = tile.info(info, j) & kTypeMask;
       double dtl[3] = {0.0, 0.0, 0.0};
       if (jr & kTouchedBit) {
         dtl[0] = l.hist[e];
@@ -814,7 +866,7 @@ __device__ __forceinline__ double force_particle(
         dtl[2] = l.hist[2 * cap + e];
       }
       double Fi[3], Mi[3];
-      pp_contact<R>(ppi[tj], sp.rolling, sp.model, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       l.hist[e] = dtl[0];
       l.hist[cap + e] = dtl[1];
       l.hist[2 * cap + e] = dtl[2];
@@ -842,7 +894,7 @@ __device__ __forceinline__ double force_particle(
                      ws.hist[(int64_t)(3 * s + 2) * n + i]};
     double Fi[3], Mi[3];
     if (t >= W.t_on && t < W.t_off) {
-      pw_contact<R>(pwi[W.material], sp.rolling, sp.model, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
+      pw_contact<R>(pwi[W.material], sp.rolling, MODEL, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
     } else {
       dtl[0] = dtl[1] = dtl[2] = 0.0;
       Fi[0] = Fi[1] = Fi[2] = 0.0;
@@ -919,18 +971,22 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
 }
 
-template <typename R, int MODE>
-__global__ void __launch_bounds__(kBlock)
+template <typename R, int MODE, int MODEL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
         const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
         ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
         double4* __restrict__ Fo, double4* __restrict__ To, const int64_t* __restrict__ clock,
         int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift) {
-  const int i = xcd_block() * kBlock + threadIdx.x;
+  const int b0 = xcd_block() * kBlock;
+  const int i = b0 + threadIdx.x;
+  __shared__ Tile tile;
+  tile.stage(in, info, b0 - kTileHalo, sp.n);
+  __syncthreads();
   double d = 0.0;
   if (i < sp.n)
-    d = force_particle<R, MODE>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo, To,
-                                clock, step_rel, flags, drift != nullptr);
+    d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo, To,
+                                clock, step_rel, flags, drift != nullptr, tile);
   if (drift) wave_max_to(drift, d);
 }
 
@@ -942,18 +998,23 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const int* flags, unsigned long long* drift, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   dim3 gr(grid_for(sp.n)), bl(kBlock);
-#define DEM_LAUNCH(RT, M)                                                                   \
-  hipLaunchKernelGGL((k_force<RT, M>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, out, info, l, \
-                     ws, F, T, clock, step_rel, flags, drift)
+#define DEM_LAUNCH(RT, M, L)                                                                \
+  hipLaunchKernelGGL((k_force<RT, M, L>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, out, info, \
+                     l, ws, F, T, clock, step_rel, flags, drift)
+#define DEM_LAUNCH_MODE(RT, L)              \
+  do {                                      \
+    if (mode == 0) DEM_LAUNCH(RT, 0, L);    \
+    else if (mode == 1) DEM_LAUNCH(RT, 1, L); \
+    else DEM_LAUNCH(RT, 2, L);              \
+  } while (0)
   if (precision == 0) {
-    if (mode == 0) DEM_LAUNCH(double, 0);
-    else if (mode == 1) DEM_LAUNCH(double, 1);
-    else DEM_LAUNCH(double, 2);
+    if (sp.model == 0) DEM_LAUNCH_MODE(double, 0);
+    else DEM_LAUNCH_MODE(double, 1);
   } else {
-    if (mode == 0) DEM_LAUNCH(float, 0);
-    else if (mode == 1) DEM_LAUNCH(float, 1);
-    else DEM_LAUNCH(float, 2);
+    if (sp.model == 0) DEM_LAUNCH_MODE(float, 0);
+    else DEM_LAUNCH_MODE(float, 1);
   }
+#undef DEM_LAUNCH_MODE
 #undef DEM_LAUNCH
   return hipGetLastError();
 }
