@@ -70,6 +70,9 @@ def _load():
         lib.ora_add_cylinder.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double,
                                          C.c_int32, C.c_int32, C.c_double, C.c_double,
                                          C.c_double, C.POINTER(C.c_int32)]
+        lib.ora_add_cone.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(C.c_int32)]
         lib.ora_step.argtypes = [P, C.c_int64]
         lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
         lib.ora_get_forces.argtypes = [P, D, D]
@@ -171,6 +174,15 @@ class OracleSim:
         _check(self._lib.ora_add_cylinder(self._h, _dp(ap), _dp(ad), radius, s_min, s_max,
                                           1 if inside else 0, material, omega, t_on, t_off,
                                           C.byref(wid)), "ora_add_cylinder")
+        return wid.value
+
+    def add_cone(self, axis_point, axis_dir, radius0, slope, s_min, s_max, inside=True,
+                 material=0, omega=0.0, t_on=-np.inf, t_off=np.inf):
+        wid = C.c_int32()
+        ap, ad = _vec(axis_point), _vec(axis_dir)
+        _check(self._lib.ora_add_cone(self._h, _dp(ap), _dp(ad), radius0, slope, s_min, s_max,
+                                      1 if inside else 0, material, omega, t_on, t_off,
+                                      C.byref(wid)), "ora_add_cone")
         return wid.value
 
     def set_particles(self, pos, radius, vel=None, omega=None, types=None):
@@ -280,10 +292,14 @@ def oracle_from_scene(scene: dict) -> OracleSim:
         if w["kind"] == "plane":
             sim.add_plane(w["point"], w["normal"], w["material"], w.get("extent"),
                           w.get("axis_point"), w.get("omega"), w["t_on"], w["t_off"])
-        else:
+        elif w["kind"] == "cylinder":
             sim.add_cylinder(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
                              w["s_max"], w["inside"], w["material"], w["omega"], w["t_on"],
                              w["t_off"])
+        else:
+            sim.add_cone(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"], w["s_min"],
+                         w["s_max"], w["inside"], w["material"], w["omega"], w["t_on"],
+                         w["t_off"])
     p = scene["particles"]
     sim.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"])
     return sim

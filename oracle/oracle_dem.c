@@ -28,6 +28,8 @@
  *             cells listed without repetition, then a fine search that keeps
  *             pairs closer than a threshold; Sec. 3.1: searched every n steps
  *   Sec. 3.7                       moving (rotating) and floating walls
+ *   walls are analytic surfaces (plane, cylinder, cone) standing in for the
+ *   paper's meshed boundaries
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
  *   - the undefined force F^c in the tangential torque is the tangential force;
@@ -65,12 +67,13 @@
 #define PI 3.14159265358979323846
 
 typedef struct {
-  int kind; /* 0 plane, 1 cylinder */
+  int kind; /* 0 plane, 1 cylinder, 2 cone */
   double p[3];     /* plane point / axis point */
   double nrm[3];   /* plane normal (into the domain) / axis direction */
   int bounded;
   double u[3], vax[3], hu, hv; /* plane extent */
-  double radius, smin, smax;   /* cylinder */
+  double radius, smin, smax;   /* cylinder; cone: radius at s = 0 */
+  double slope;                /* cone: radius grows by slope per unit s */
   int inside;
   int material;
   double omega[3]; /* angular velocity vector of the wall */
@@ -304,6 +307,54 @@ typedef struct {
   double n[3], dn, xc[3];
 } ora_wgeo;
 
+/* Cone (frustum) around the axis through p along nrm: at axial coordinate s
+   the surface lies at distance r(s) = radius + slope s from the axis.  A
+   particle whose centre has s in [smin, smax] and lies at rho from the axis
+   is at distance (r(s) - rho) / q from the surface line of its meridian
+   (inside; rho - r(s) for outside), q = sqrt(1 + slope^2).  The predicates
+   compare rho^2 with squared bounds, as for the cylinder.  The outward
+   surface normal of the meridian is (e_rho - slope nrm) / q. */
+static void cone_geometry(const ora_wall* W, const double* x, const double* rel, double R,
+                          double skin, ora_wgeo* g) {
+  double sax = vdot(rel, W->nrm);
+  if (!(sax >= W->smin && sax <= W->smax)) return;
+  double r[3] = {rel[0] - sax * W->nrm[0], rel[1] - sax * W->nrm[1],
+                 rel[2] - sax * W->nrm[2]};
+  double rho2 = vdot(r, r);
+  if (!(rho2 > 0.0)) return;
+  double q = sqrt(1.0 + W->slope * W->slope);
+  double rs = W->radius + W->slope * sax;
+  if (W->inside) {
+    /* candidate: r(s) - (R + s) q < rho < r(s) + R q; touching: rho > r(s) - R q */
+    double lo = rs - (R + skin) * q;
+    double hi = rs + R * q;
+    int above_lo = (lo <= 0.0) || (rho2 > lo * lo);
+    g->candidate = above_lo && (hi > 0.0) && (rho2 < hi * hi);
+    double lt = rs - R * q;
+    g->touching = (lt <= 0.0) || (rho2 > lt * lt);
+  } else {
+    /* candidate: r(s) - R q < rho < r(s) + (R + s) q; touching: rho < r(s) + R q */
+    double hi = rs + (R + skin) * q;
+    double lo = rs - R * q;
+    int above_lo = (lo <= 0.0) || (rho2 > lo * lo);
+    g->candidate = above_lo && (hi > 0.0) && (rho2 < hi * hi);
+    double lt = rs + R * q;
+    g->touching = (lt > 0.0) && (rho2 < lt * lt);
+  }
+  if (g->touching) {
+    double rho = sqrt(rho2);
+    double er[3] = {r[0] / rho, r[1] / rho, r[2] / rho};
+    double m[3] = {(er[0] - W->slope * W->nrm[0]) / q, (er[1] - W->slope * W->nrm[1]) / q,
+                   (er[2] - W->slope * W->nrm[2]) / q};
+    double dist = W->inside ? (rs - rho) / q : (rho - rs) / q;
+    g->dn = R - dist;
+    for (int k = 0; k < 3; ++k) {
+      g->n[k] = W->inside ? m[k] : -m[k];
+      g->xc[k] = x[k] + dist * g->n[k];
+    }
+  }
+}
+
 static void wall_geometry(const ora_wall* W, const double* x, double R, double skin,
                           ora_wgeo* g) {
   g->candidate = g->touching = 0;
@@ -324,6 +375,10 @@ static void wall_geometry(const ora_wall* W, const double* x, double R, double s
       }
       g->dn = R - dist;
     }
+    return;
+  }
+  if (W->kind == 2) {
+    cone_geometry(W, x, rel, R, skin, g);
     return;
   }
   /* cylinder */
@@ -879,6 +934,38 @@ int ora_add_cylinder(ora_sim* s, const double axis_point[3], const double axis_d
     W.omega[k] = omega * W.nrm[k];
   }
   W.radius = radius;
+  W.smin = s_min;
+  W.smax = s_max;
+  W.inside = inside ? 1 : 0;
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  s->walls[s->nw] = W;
+  if (wall_id) *wall_id = s->nw;
+  s->nw += 1;
+  return ORA_OK;
+}
+
+int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3],
+                 double radius0, double slope, double s_min, double s_max, int32_t inside,
+                 int32_t material, double omega, double t_on, double t_off, int32_t* wall_id) {
+  if (!s || !axis_point || !axis_dir || s->nw >= ORA_MAX_WALLS) return ORA_EINVAL;
+  if (material < 0 || material >= ORA_MAX_TYPES || !s->mat_set[material]) return ORA_EINVAL;
+  if (!(s_max >= s_min) || !isfinite(slope)) return ORA_EINVAL;
+  /* the surface must stay away from the axis over the whole range */
+  if (!(radius0 + slope * s_min > 0.0) || !(radius0 + slope * s_max > 0.0)) return ORA_EINVAL;
+  if (s->n > 0) return ORA_ESTATE;
+  ora_wall W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 2;
+  if (unit3(axis_dir, W.nrm)) return ORA_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = axis_point[k];
+    W.ax[k] = axis_point[k];
+    W.omega[k] = omega * W.nrm[k];
+  }
+  W.radius = radius0;
+  W.slope = slope;
   W.smin = s_min;
   W.smax = s_max;
   W.inside = inside ? 1 : 0;

@@ -65,6 +65,11 @@ int ora_add_cylinder(ora_sim* s, const double axis_point[3], const double axis_d
                      double radius, double s_min, double s_max, int32_t inside,
                      int32_t material, double omega, double t_on, double t_off,
                      int32_t* wall_id);
+/* Cone around the axis: surface radius radius0 + slope s at axial coordinate
+   s in [s_min, s_max] (s measured from axis_point along axis_dir). */
+int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3],
+                 double radius0, double slope, double s_min, double s_max, int32_t inside,
+                 int32_t material, double omega, double t_on, double t_off, int32_t* wall_id);
 int ora_step(ora_sim* s, int64_t n_steps);
 int ora_get_state(ora_sim* s, double* pos, double* vel, double* omega, uint8_t* active,
                   double* time_out);

@@ -17,6 +17,8 @@ Scene dictionary layout::
      "walls": [dict(kind="plane", point, normal, material, extent=None,
                     axis_point=None, omega=None, t_on, t_off) |
                dict(kind="cylinder", axis_point, axis_dir, radius, s_min, s_max,
+                    inside, material, omega, t_on, t_off) |
+               dict(kind="cone", axis_point, axis_dir, radius0, slope, s_min, s_max,
                     inside, material, omega, t_on, t_off), ...],
      "particles": {pos (n,3), radius (n,), vel (n,3), omega (n,3), types (n,)}}
 """
@@ -67,6 +69,15 @@ def cylinder(axis_point, axis_dir, radius, s_min, s_max, inside=True, material=0
                 radius=float(radius), s_min=float(s_min), s_max=float(s_max),
                 inside=bool(inside), material=material, omega=float(omega), t_on=t_on,
                 t_off=t_off)
+
+
+def cone(axis_point, axis_dir, radius0, slope, s_min, s_max, inside=True, material=0,
+         omega=0.0, t_on=-INF, t_off=INF):
+    """Cone (frustum) whose surface lies at radius0 + slope * s from the axis."""
+    return dict(kind="cone", axis_point=tuple(axis_point), axis_dir=tuple(axis_dir),
+                radius0=float(radius0), slope=float(slope), s_min=float(s_min),
+                s_max=float(s_max), inside=bool(inside), material=material,
+                omega=float(omega), t_on=t_on, t_off=t_off)
 
 
 def box_walls(lo, hi, material=0):
