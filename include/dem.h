@@ -154,6 +154,24 @@ int dem_add_cylinder_wall(dem_ctx* ctx, int32_t instance, const double axis_poin
                           int32_t inside, int32_t material, double omega, double t_on,
                           double t_off, int32_t* wall_id);
 
+/* Conical wall (frustum) around the axis through axis_point along axis_dir
+   (normalised): at axial coordinate s = (x - axis_point).axis_dir the
+   surface lies at radius0 + slope s from the axis (slope = cot of the
+   surface's angle to the axis-normal plane, negative when the cone narrows
+   with s), acting where s of the particle centre lies in [s_min, s_max]; the
+   radius must stay > 0 there (DEM_EINVAL otherwise).  A particle at distance
+   rho from the axis is at (r(s) - rho) / sqrt(1 + slope^2) from the surface
+   of its meridian (inside != 0; the opposite sign outside), and is pushed
+   along that meridian's surface normal.  Walls are analytic surfaces here,
+   standing in for the paper's meshed boundaries (Sec. 2.1, last paragraph:
+   the wall acts as a body of infinite mass and radius); a cone closes the
+   hopper of a cylindrical silo.  Spins at `omega` rad/s about the axis;
+   activity window and ordering rules as for the planar wall. */
+int dem_add_cone_wall(dem_ctx* ctx, int32_t instance, const double axis_point[3],
+                      const double axis_dir[3], double radius0, double slope, double s_min,
+                      double s_max, int32_t inside, int32_t material, double omega, double t_on,
+                      double t_off, int32_t* wall_id);
+
 /* Set n >= 0 particles of one instance: positions (n x 3), velocities and
    angular velocities (n x 3, NULL = zero), radii (n, > 0) and material types
    (n, NULL = type 0; each type's material must be set).  Masses are

@@ -1058,6 +1058,44 @@ int dem_add_cylinder_wall(dem_ctx* c, int32_t instance, const double axis_point[
   return DEM_OK;
 }
 
+int dem_add_cone_wall(dem_ctx* c, int32_t instance, const double axis_point[3],
+                      const double axis_dir[3], double radius0, double slope, double s_min,
+                      double s_max, int32_t inside, int32_t material, double omega, double t_on,
+                      double t_off, int32_t* wall_id) {
+  if (!c || !axis_point || !axis_dir) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if ((int)I.walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !I.mat_set[material])
+    return set_err(DEM_EINVAL, "wall material %d not set", material);
+  if (!(s_max >= s_min) || !std::isfinite(slope) || !std::isfinite(radius0))
+    return set_err(DEM_EINVAL, "cone needs finite radius0 and slope and s_max >= s_min");
+  if (!(radius0 + slope * s_min > 0.0) || !(radius0 + slope * s_max > 0.0))
+    return set_err(DEM_EINVAL, "cone radius must stay > 0 over [s_min, s_max]");
+  if (I.staged) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  WallDev W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 2;
+  if (!unit3(axis_dir, W.nrm)) return set_err(DEM_EINVAL, "zero or non-finite axis");
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = axis_point[k];
+    W.ax[k] = axis_point[k];
+    W.omega[k] = omega * W.nrm[k];
+  }
+  W.radius = radius0;
+  W.slope = slope;
+  W.q = sqrt(1.0 + slope * slope);
+  W.smin = s_min;
+  W.smax = s_max;
+  W.inside = inside ? 1 : 0;
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  if (wall_id) *wall_id = (int32_t)I.walls.size();
+  I.walls.push_back(W);
+  return DEM_OK;
+}
+
 int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos,
                       const double* vel, const double* omega, const double* radius,
                       const int32_t* type) {

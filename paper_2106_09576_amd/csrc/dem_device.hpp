@@ -40,7 +40,8 @@ struct PairCoef {
 };
 
 // Analytic wall.  kind 0: plane (point p, unit normal nrm into the domain,
-// optional rectangular extent along u / vax).  kind 1: cylinder (axis point p,
+// optional rectangular extent along u / vax).  kind 2: cone, as the cylinder
+// with the surface at radius + slope s.  kind 1: cylinder (axis point p,
 // unit axis nrm, radius, axial range [smin, smax], particles inside or
 // outside).  Rotation: surface velocity omega x (x_c - ax).  Active for
 // t_on <= t < t_off.
@@ -51,6 +52,7 @@ struct WallDev {
   double omega[3], ax[3];
   double t_on, t_off;
   double skin;  // the owning instance's skin (contact-search margin)
+  double slope, q;  // cone: radius + slope s at axial coordinate s; q = sqrt(1 + slope^2)
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).

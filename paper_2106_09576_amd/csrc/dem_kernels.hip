@@ -294,6 +294,39 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
   double r[3] = {rel[0] - sax * W.nrm[0], rel[1] - sax * W.nrm[1], rel[2] - sax * W.nrm[2]};
   double rho2 = dot3(r, r);
   if (!(rho2 > 0.0)) return;
+  if (W.kind == 2) {
+    // cone: distance (r(s) - rho) / q inside, (rho - r(s)) / q outside, tested
+    // as rho^2 against squared bounds; outward normal (e_rho - slope nrm) / q
+    const double q = W.q;
+    const double rs = W.radius + W.slope * sax;
+    if (W.inside) {
+      double lo = rs - (R + skin) * q;
+      double hi = rs + R * q;
+      bool above = (lo <= 0.0) || (rho2 > lo * lo);
+      g.candidate = above && (hi > 0.0) && (rho2 < hi * hi);
+      double lt = rs - R * q;
+      g.touching = (lt <= 0.0) || (rho2 > lt * lt);
+    } else {
+      double hi = rs + (R + skin) * q;
+      double lo = rs - R * q;
+      bool above = (lo <= 0.0) || (rho2 > lo * lo);
+      g.candidate = above && (hi > 0.0) && (rho2 < hi * hi);
+      double lt = rs + R * q;
+      g.touching = (lt > 0.0) && (rho2 < lt * lt);
+    }
+    if (g.touching && need_contact) {
+      double rho = sqrt(rho2);
+      double er[3] = {r[0] / rho, r[1] / rho, r[2] / rho};
+      double dist = W.inside ? (rs - rho) / q : (rho - rs) / q;
+      g.dn = R - dist;
+      for (int k = 0; k < 3; ++k) {
+        const double m = (er[k] - W.slope * W.nrm[k]) / q;
+        g.n[k] = W.inside ? m : -m;
+        g.xc[k] = x[k] + dist * g.n[k];
+      }
+    }
+    return;
+  }
   const double Rc = W.radius;
   if (W.inside) {
     double lo = Rc - (R + skin);

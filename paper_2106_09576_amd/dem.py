@@ -79,6 +79,9 @@ SIGNATURES = {
     "dem_add_cylinder_wall": (C.c_int, [P, C.c_int32, DP, DP, C.c_double, C.c_double,
                                         C.c_double, C.c_int32, C.c_int32, C.c_double,
                                         C.c_double, C.c_double, I32P]),
+    "dem_add_cone_wall": (C.c_int, [P, C.c_int32, DP, DP, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.c_double, I32P]),
     "dem_set_particles": (C.c_int, [P, C.c_int32, C.c_int64, DP, DP, DP, DP, I32P]),
     "dem_set_particles_device": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, P, P]),
     "dem_commit": (C.c_int, [P]),
@@ -203,6 +206,15 @@ class Dem:
                                                     t_on, t_off, C.byref(wid)))
         return wid.value
 
+    def add_cone_wall(self, axis_point, axis_dir, radius0, slope, s_min, s_max, inside=True,
+                      material=0, omega=0.0, t_on=-np.inf, t_off=np.inf, instance=0):
+        wid = C.c_int32()
+        ap, ad = _v3(axis_point), _v3(axis_dir)
+        self._check(self._lib.dem_add_cone_wall(self._h, instance, _d(ap), _d(ad), radius0, slope,
+                                                s_min, s_max, 1 if inside else 0, material, omega,
+                                                t_on, t_off, C.byref(wid)))
+        return wid.value
+
     def set_particles(self, pos, radius, vel=None, omega=None, types=None, instance=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
         n = pos.shape[0]
@@ -310,10 +322,14 @@ class Dem:
                 self.add_planar_wall(w["point"], w["normal"], w["material"], w.get("extent"),
                                      w.get("axis_point"), w.get("omega"), w["t_on"], w["t_off"],
                                      instance=instance)
-            else:
+            elif w["kind"] == "cylinder":
                 self.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
                                        w["s_max"], w["inside"], w["material"], w["omega"],
                                        w["t_on"], w["t_off"], instance=instance)
+            else:
+                self.add_cone_wall(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"],
+                                   w["s_min"], w["s_max"], w["inside"], w["material"],
+                                   w["omega"], w["t_on"], w["t_off"], instance=instance)
         p = scene["particles"]
         self.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"],
                            instance=instance)

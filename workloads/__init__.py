@@ -210,6 +210,132 @@ def drum_scene(n=1_000_000, d=3.0e-3, R_drum=None, L=None, omega=1.0, seed=2,
                 geometry=dict(R=R_drum, L=L, omega=omega))
 
 
+def _fill_from_bottom(lo, hi, spacing, jitter, clearance_ok, n, rng, what):
+    """The n lowest points of a jittered lattice over [lo, hi] that pass
+    clearance_ok (a vectorised test on an (m, 3) array), shuffled."""
+    g = jittered_lattice(lo, hi, spacing, jitter, rng)
+    g = g[clearance_ok(g)]
+    if g.shape[0] < n:
+        raise RuntimeError(f"{what}: only {g.shape[0]} lattice sites for {n} spheres")
+    order = np.lexsort((g[:, 0], g[:, 1], g[:, 2]))
+    g = g[order[:n]]
+    return g[rng.permutation(n)]
+
+
+SILO_MATERIAL = dict(BOX_MATERIAL)
+
+
+def wedge_silo_scene(n=200_000, d_min=2.0e-3, d_max=3.0e-3, width=0.2, depth=0.04,
+                     height=0.9, outlet=0.012, angle_deg=30.0, t_open=INF, seed=1,
+                     dt=5.0e-6, K=20, spacing=1.02, clearance=1.02, threshold=1.3,
+                     material=None):
+    """Wedge-shaped silo: a box (x across, y through the depth, z up) whose
+    floor is two planes inclined at angle_deg from the horizontal meeting a
+    slot outlet of width `outlet` at z = 0, plugged by a floating plane that
+    disappears at t_open.  Diameters uniform in [d_min, d_max]; spheres start
+    at rest on a jittered lattice of spacing `spacing` d_max filling the silo
+    from the bottom, at least `clearance` radii from every wall.  The domain
+    box ends 2 d_max below the outlet: spheres that leave become inactive."""
+    mat = dict(SILO_MATERIAL if material is None else material)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = math.radians(angle_deg)
+    sa, ca = math.sin(a), math.cos(a)
+    ho = outlet / 2
+    run = width / 2 - ho                  # horizontal extent of one wedge plane
+    rise = run * math.tan(a)
+    hl = 0.5 * run / ca                   # half length along the slope
+    hv = depth / 2 + d_max
+    nL, nR = (sa, 0.0, ca), (-sa, 0.0, ca)
+    pL = (-ho - run / 2, 0.0, rise / 2)
+    pR = (ho + run / 2, 0.0, rise / 2)
+    walls = [
+        plane(pL, nL, 0, (-ca, 0.0, sa, hl, hv)),
+        plane(pR, nR, 0, (ca, 0.0, sa, hl, hv)),
+        plane((-width / 2, 0.0, 0.0), (1.0, 0.0, 0.0)),
+        plane((width / 2, 0.0, 0.0), (-1.0, 0.0, 0.0)),
+        plane((0.0, -depth / 2, 0.0), (0.0, 1.0, 0.0)),
+        plane((0.0, depth / 2, 0.0), (0.0, -1.0, 0.0)),
+        plane((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 0, (1.0, 0.0, 0.0, ho + 0.25 * d_max, hv),
+              t_off=t_open),
+    ]
+    c = clearance * d_max / 2
+
+    def ok(g):
+        dl = (g[:, 0] - pL[0]) * nL[0] + (g[:, 2] - pL[2]) * nL[2]
+        dr = (g[:, 0] - pR[0]) * nR[0] + (g[:, 2] - pR[2]) * nR[2]
+        return ((dl >= c) & (dr >= c) & (g[:, 2] >= c) & (np.abs(g[:, 0]) <= width / 2 - c)
+                & (np.abs(g[:, 1]) <= depth / 2 - c) & (g[:, 2] <= height - c))
+
+    g = _fill_from_bottom((-width / 2, -depth / 2, 0.0), (width / 2, depth / 2, height),
+                          spacing * d_max, 0.01 * d_max, ok, n, rng, "wedge silo")
+    radius = rng.uniform(d_min, d_max, n) / 2
+    m = 2 * d_max
+    lo = (-width / 2 - m, -depth / 2 - m, -2 * d_max)
+    hi = (width / 2 + m, depth / 2 + m, height + m)
+    return dict(name=f"wedge_silo_{n}", config=_cfg(dt, lo, hi, threshold=threshold, K=K),
+                materials=[mat], walls=walls, particles=_particles(g, radius),
+                geometry=dict(width=width, depth=depth, height=height, outlet=outlet,
+                              angle_deg=angle_deg))
+
+
+HOPPER_MATERIAL = dict(BOX_MATERIAL, youngs=1.0e7, friction=0.4)
+
+
+def lognormal_diameters(n, mean, sigma, lo, hi, rng):
+    """Log-normal diameters with mean `mean` and standard deviation `sigma` of
+    ln d, clamped to [lo, hi]."""
+    mu = math.log(mean) - sigma * sigma / 2
+    return np.clip(np.exp(rng.normal(mu, sigma, n)), lo, hi)
+
+
+def hopper_silo_scene(n=4_300_000, d_mean=2.5e-3, sigma=0.1, d_lo=2.0e-3, d_hi=3.5e-3,
+                      R=0.25, H=1.0, outlet=0.04, angle_deg=60.0, t_open=INF, seed=3,
+                      dt=2.0e-6, K=20, spacing=1.02, clearance=1.02, threshold=1.3,
+                      material=None):
+    """Cylindrical silo with a conical hopper: a cone around the vertical axis
+    from the outlet radius at z = 0, inclined at angle_deg from the horizontal,
+    up to radius R, then a cylinder of radius R and height H (taller when the
+    spheres need it to start on the lattice).  The outlet is plugged by a
+    floating plane until t_open.  Log-normal diameters; spheres start at rest
+    on a jittered lattice filling the silo from the bottom."""
+    mat = dict(HOPPER_MATERIAL if material is None else material)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = lognormal_diameters(n, d_mean, sigma, d_lo, d_hi, rng)
+    dmax = float(d.max()) if n else d_hi
+    r0 = outlet / 2
+    slope = 1.0 / math.tan(math.radians(angle_deg))
+    s_top = (R - r0) / slope
+    q = math.sqrt(1.0 + slope * slope)
+    c = clearance * dmax / 2
+    a = spacing * dmax
+    # the lattice holds about (pi R^2 / a^2) spheres per layer of height a
+    per_layer = math.pi * (R - c) ** 2 / (a * a)
+    need = s_top + 1.3 * a * n / max(per_layer, 1.0) + a
+    top = s_top + max(H, need)
+
+    def ok(g):
+        rho = np.sqrt(g[:, 0] ** 2 + g[:, 1] ** 2)
+        z = g[:, 2]
+        in_cone = (z < s_top) & (rho <= r0 + slope * z - c * q)
+        in_cyl = (z >= s_top) & (rho <= R - c)
+        return (in_cone | in_cyl) & (z >= c) & (z <= top - c)
+
+    g = _fill_from_bottom((-R, -R, 0.0), (R, R, top), a, 0.01 * dmax, ok, n, rng, "hopper silo")
+    walls = [
+        cone((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), r0, slope, 0.0, s_top, True),
+        cylinder((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), R, s_top, top, True),
+        plane((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 0,
+              (1.0, 0.0, 0.0, r0 + 0.5 * dmax, r0 + 0.5 * dmax), t_off=t_open),
+    ]
+    m = 2 * dmax
+    lo = (-R - m, -R - m, -2 * dmax)
+    hi = (R + m, R + m, top + m)
+    return dict(name=f"hopper_silo_{n}", config=_cfg(dt, lo, hi, threshold=threshold, K=K),
+                materials=[mat], walls=walls, particles=_particles(g, d / 2),
+                geometry=dict(R=R, H=top - s_top, outlet=outlet, angle_deg=angle_deg,
+                              cone_top=s_top))
+
+
 def dense_snapshot(n=3000, d=3.0e-3, seed=7, overlap=0.01, vmax=0.05, wmax=20.0,
                    polydisperse=0.0, n_types=1, dt=1.0e-5, K=5, walls=True,
                    rolling="constant", integrator="verlet", friction=None,
