@@ -96,6 +96,9 @@ typedef struct {
   int32_t reserved;          /* must be 0 */
   double characteristic_velocity; /* V of Eq. (linearkn) [m/s], > 0 for the
                                      linear model, ignored otherwise */
+  int32_t force_block;       /* threads per force workgroup: 64, 128 or 256;
+                                0 = 256 (results do not depend on it) */
+  int32_t reserved2;         /* must be 0 */
 } dem_config;
 
 typedef struct {
@@ -250,6 +253,36 @@ int dem_get_stats(dem_ctx* ctx, dem_stats* out);
 
 /* Stream the library launches on (hipStream_t), for timing with events. */
 void* dem_stream(dem_ctx* ctx);
+
+/* Result of dem_autotune. */
+typedef struct {
+  int32_t force_block;       /* chosen threads per force workgroup            */
+  int32_t rebuild_interval;  /* chosen search schedule: K >= 1, 0 = dynamic   */
+  double cell_factor;        /* chosen cell edge / d_max                      */
+  double ms_per_step;        /* whole step with the chosen settings           */
+  int64_t steps;             /* simulation steps the trials advanced          */
+  double block_ms[3];        /* force kernel ms with 64, 128, 256 threads     */
+  double cell_factors[4];    /* cell edges / d_max tried                      */
+  double search_ms[4];       /* ms per contact search with each of them       */
+  int32_t schedules[8];      /* schedules tried (K, 0 = dynamic, -1 unused)   */
+  double schedule_ms[8];     /* ms per step with each (-1: not tried, a
+                                constant K too long for the measured drift)   */
+} dem_tuning;
+
+/* Pick, by measurement on the running simulation, the threads per workgroup
+   of the force kernel (64, 128, 256: force-kernel time), the cell edge (from
+   r_s / d_max up to 1.5 times that: time of a contact search) and the search
+   schedule (dynamic and K = 5..80: whole steps per second), and keep them.
+   Contact searches are the constant/dynamic approaches of Sec. 3.1; the cell
+   edge and block size change no result beyond summation order.  Every trial
+   is trial_steps (10..100000) ordinary steps of the simulation, so the call
+   advances it (out->steps steps, plus forced re-sorts); constant K are tried
+   only while K times the largest per-step drift measured in the dynamic
+   trial stays below a quarter of half the skin.  The choice depends on
+   timings, so runs that must be bitwise reproducible fix their settings
+   instead.  Errors of the steps (DEM_EUNSTABLE ...) are returned as from
+   dem_step. */
+int dem_autotune(dem_ctx* ctx, int32_t trial_steps, dem_tuning* out);
 
 /* Benchmark instrumentation.  While enabled, dem_step launches every kernel
    directly (no graphs) and records HIP events around each force launch and

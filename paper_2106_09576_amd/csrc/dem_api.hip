@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -82,7 +83,11 @@ struct dem_ctx {
   int64_t n_keys = 0;
 
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
   size_t dev_bytes = 0;
+  int force_block = kBlock;  // threads per force workgroup (64, 128, 256)
+  double cell_factor = 0.0;  // cell edge / d_max of the grids in use
+  uint32_t* d_mort = nullptr;
   double4 *pos[2]{}, *vel[2]{}, *omg[2]{};
   int *gid[2]{}, *info[2]{};
   double4 *F[2]{}, *T[2]{};
@@ -145,8 +150,22 @@ int dalloc(dem_ctx* c, void** p, size_t bytes) {
     return set_err(DEM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
   }
   c->allocs.push_back(*p);
+  c->alloc_bytes.push_back(bytes);
   c->dev_bytes += bytes;
   return DEM_OK;
+}
+
+// Free one allocation made by dalloc (after the stream has drained).
+void dfree(dem_ctx* c, void* p) {
+  if (!p) return;
+  for (size_t k = 0; k < c->allocs.size(); ++k)
+    if (c->allocs[k] == p) {
+      (void)hipFree(p);
+      c->dev_bytes -= c->alloc_bytes[k];
+      c->allocs.erase(c->allocs.begin() + (long)k);
+      c->alloc_bytes.erase(c->alloc_bytes.begin() + (long)k);
+      return;
+    }
 }
 
 template <typename T>
@@ -178,7 +197,9 @@ void free_particles(dem_ctx* c) {
   }
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
+  c->alloc_bytes.clear();
   c->dev_bytes = 0;
+  c->d_mort = nullptr;
   c->ready = false;
   c->n = 0;
 }
@@ -286,7 +307,7 @@ int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* dr
   HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_inst, c->d_pp, c->d_pw, c->d_walls,
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
-                      c->d_clock, step_rel, c->d_flags, drift, c->stream));
+                      c->d_clock, step_rel, c->d_flags, drift, c->force_block, c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }
@@ -611,6 +632,136 @@ int snapshot(dem_ctx* c, HostSnapshot& h, bool want_pos, bool want_vel, bool wan
 
 int commit(dem_ctx* c);
 
+// Cell grid of every instance for the cell edge h = cf d_max (1 + 1e-9),
+// never below the search radius r_s: cell counts, Morton bit widths and one
+// key range per instance.  The instances keep their previous grids when the
+// new ones would not fit.
+int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* mort_total_out) {
+  const int B = (int)c->inst.size();
+  std::vector<GridDev> grids((size_t)B);
+  std::vector<uint32_t> bases((size_t)B);
+  std::vector<double> hs((size_t)B);
+  int64_t total_keys = 0;
+  size_t mort_total = 0;
+  for (int b = 0; b < B; ++b) {
+    const Instance& I = c->inst[(size_t)b];
+    const double h = std::max(cf * I.dmax * (1.0 + 1e-9), I.rs);
+    GridDev g;
+    memset(&g, 0, sizeof(g));
+    int bits_total = 0;
+    for (int k = 0; k < 3; ++k) {
+      g.lo[k] = I.own_domain ? I.lo[k] : c->cfg.domain_lo[k];
+      g.hi[k] = I.own_domain ? I.hi[k] : c->cfg.domain_hi[k];
+      const double span = g.hi[k] - g.lo[k];
+      const double cc = I.n > 0 ? ceil(span / h) : 1.0;
+      if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
+      g.nc[k] = std::max(1, (int)cc);
+      int bb = 0;
+      while ((1 << bb) < g.nc[k]) ++bb;
+      g.bits[k] = bb;
+      bits_total += bb;
+      mort_total += (size_t)g.nc[k];
+    }
+    if (bits_total > 30)
+      return set_err(DEM_EINVAL, "instance %d: cell grid %dx%dx%d is too large; shrink the domain",
+                     b, g.nc[0], g.nc[1], g.nc[2]);
+    g.h = I.n > 0 ? h : 1.0;
+    g.n_keys = (int64_t)1 << bits_total;
+    grids[(size_t)b] = g;
+    hs[(size_t)b] = h;
+    bases[(size_t)b] = (uint32_t)total_keys;
+    total_keys += g.n_keys;
+    if (total_keys >= ((int64_t)1 << 30))
+      return set_err(DEM_EINVAL, "the cell grids of the batch need more than 2^30 cells");
+  }
+  for (int b = 0; b < B; ++b) {
+    Instance& I = c->inst[(size_t)b];
+    I.grid = grids[(size_t)b];
+    I.h = hs[(size_t)b];
+    I.key_base = bases[(size_t)b];
+  }
+  c->cell_factor = cf;
+  *total_keys_out = total_keys;
+  *mort_total_out = mort_total;
+  return DEM_OK;
+}
+
+// Morton tables of the instance grids (bit b of axis a goes to the next free
+// key bit, taking levels b = 0, 1, ... and axes x, y, z in turn; the tables
+// live at c->d_mort) and the instance table.
+void grid_tables(dem_ctx* c, std::vector<uint32_t>* hmort, std::vector<InstDev>* hinst) {
+  const int B = (int)c->inst.size();
+  hmort->clear();
+  hinst->assign((size_t)B, InstDev{});
+  for (int b = 0; b < B; ++b) {
+    Instance& I = c->inst[(size_t)b];
+    GridDev& g = I.grid;
+    int pos_of[3][32];
+    int next = 0;
+    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
+    for (int lvl = 0; lvl < maxb; ++lvl)
+      for (int a = 0; a < 3; ++a)
+        if (lvl < g.bits[a]) pos_of[a][lvl] = next++;
+    for (int a = 0; a < 3; ++a) {
+      g.mort[a] = c->d_mort + hmort->size();
+      for (int ci = 0; ci < g.nc[a]; ++ci) {
+        uint32_t key = 0;
+        for (int lvl = 0; lvl < g.bits[a]; ++lvl)
+          if ((ci >> lvl) & 1) key |= 1u << pos_of[a][lvl];
+        hmort->push_back(key);
+      }
+    }
+    InstDev& D = (*hinst)[(size_t)b];
+    D.grid = g;
+    D.key_base = I.key_base;
+    D.wall_begin = I.w_begin;
+    D.wall_end = I.w_begin + (int)I.walls.size();
+    D.coef_base = b * kMaxTypes * kMaxTypes;
+    D.rs2 = I.rs * I.rs;
+    D.guard2 = (0.5 * I.skin) * (0.5 * I.skin);
+    D.skin = I.skin;
+    D.ihs = I.skin > 0.0 ? 2.0 / I.skin : 0.0;
+  }
+}
+
+// Change the cell edge of a built batch to cf d_max.  The neighbour lists do
+// not depend on the grid, so the next contact search simply uses the new
+// cells (histories are carried as at every search).
+int regrid(dem_ctx* c, double cf) {
+  int64_t total_keys = 0;
+  size_t mort_total = 0;
+  int rc = plan_grids(c, cf, &total_keys, &mort_total);
+  if (rc) return rc;
+  destroy_graphs(c);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  dfree(c, c->count);
+  dfree(c, c->start);
+  dfree(c, c->tile_sums);
+  dfree(c, c->d_mort);
+  c->count = c->start = c->tile_sums = nullptr;
+  c->d_mort = nullptr;
+  rc = rc ? rc : dalloc_t(c, &c->count, (size_t)total_keys + 1);
+  rc = rc ? rc : dalloc_t(c, &c->start, (size_t)total_keys + 2);
+  rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((total_keys + 1 + 1023) / 1024 + 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
+  if (rc) {
+    c->failed = true;
+    return rc;
+  }
+  std::vector<uint32_t> hmort;
+  std::vector<InstDev> hinst;
+  grid_tables(c, &hmort, &hinst);
+  if (!hmort.empty())
+    HIPCHK(hipMemcpyAsync(c->d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->n_keys = total_keys;
+  c->sp.n_keys = (uint32_t)total_keys;
+  return DEM_OK;
+}
+
 // The batch is built on the device at the first call that needs it.
 int require_ready(dem_ctx* c) {
   if (!c) return set_err(DEM_EINVAL, "null context");
@@ -648,32 +799,7 @@ int commit(dem_ctx* c) {
     // search geometry: r_s = min(threshold, cell_factor) d_max, h >= r_s
     I.dmax = 2.0 * rmax;
     I.rs = f * I.dmax;
-    I.h = c->cfg.cell_factor * I.dmax * (1.0 + 1e-9);
     I.skin = I.rs - I.dmax;
-    GridDev& g = I.grid;
-    int bits_total = 0;
-    for (int k = 0; k < 3; ++k) {
-      g.lo[k] = I.own_domain ? I.lo[k] : c->cfg.domain_lo[k];
-      g.hi[k] = I.own_domain ? I.hi[k] : c->cfg.domain_hi[k];
-      const double span = g.hi[k] - g.lo[k];
-      const double cc = I.n > 0 ? ceil(span / I.h) : 1.0;
-      if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
-      g.nc[k] = std::max(1, (int)cc);
-      int bb = 0;
-      while ((1 << bb) < g.nc[k]) ++bb;
-      g.bits[k] = bb;
-      bits_total += bb;
-      mort_total += (size_t)g.nc[k];
-    }
-    if (bits_total > 30)
-      return set_err(DEM_EINVAL, "instance %d: cell grid %dx%dx%d is too large; shrink the domain",
-                     b, g.nc[0], g.nc[1], g.nc[2]);
-    g.h = I.n > 0 ? I.h : 1.0;
-    g.n_keys = (int64_t)1 << bits_total;
-    I.key_base = (uint32_t)total_keys;
-    total_keys += g.n_keys;
-    if (total_keys >= ((int64_t)1 << 30))
-      return set_err(DEM_EINVAL, "the cell grids of the batch need more than 2^30 cells");
     if (I.n > 0) {
       // spheres of radius rmin whose centres lie within r_s of a centre fit in a
       // ball of radius r_s + rmin (packing density <= 0.7405), 25% margin
@@ -683,16 +809,23 @@ int commit(dem_ctx* c) {
     I.w_begin = n_walls;
     n_walls += (int)I.walls.size();
   }
+  {
+    int rc = plan_grids(c, c->cfg.cell_factor, &total_keys, &mort_total);
+    if (rc) return rc;
+  }
   c->dynamic = c->cfg.rebuild_interval == 0;
   double ihs_max = 0.0, rate0 = 0.0, ihs_min = HUGE_VAL;
-  if (c->dynamic) {
+  bool all_skins = true;
+  for (int b = 0; b < B; ++b)
+    if (c->inst[(size_t)b].n > 0 && !(c->inst[(size_t)b].skin > 0.0)) all_skins = false;
+  if (c->dynamic && !all_skins)
+    return set_err(DEM_EINVAL,
+                   "dynamic search (rebuild_interval 0) needs a skin: neighbor_threshold "
+                   "and cell_factor must exceed 1");
+  if (all_skins) {
     for (int b = 0; b < B; ++b) {
       const Instance& I = c->inst[(size_t)b];
       if (I.n == 0) continue;
-      if (!(I.skin > 0.0))
-        return set_err(DEM_EINVAL,
-                       "dynamic search (rebuild_interval 0) needs a skin: neighbor_threshold "
-                       "and cell_factor must exceed 1");
       const double ihs = 2.0 / I.skin;
       ihs_max = std::max(ihs_max, ihs);
       ihs_min = std::min(ihs_min, ihs);
@@ -760,8 +893,7 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
-  uint32_t* d_mort = nullptr;
-  rc = rc ? rc : dalloc_t(c, &d_mort, std::max<size_t>(mort_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
   if (rc == DEM_OK) {
     hipError_t he = hipHostMalloc((void**)&c->h_drift,
@@ -777,44 +909,17 @@ int commit(dem_ctx* c) {
     return rc;
   }
 
-  // Morton tables (bit b of axis a goes to the next free key bit, taking
-  // levels b = 0, 1, ... and axes x, y, z in turn), instance table, walls and
-  // material-pair tables
+  // Morton tables, instance table, walls and material-pair tables
   std::vector<uint32_t> hmort;
-  hmort.reserve(mort_total);
-  std::vector<InstDev> hinst((size_t)B);
+  std::vector<InstDev> hinst;
+  grid_tables(c, &hmort, &hinst);
   std::vector<WallDev> hwalls;
   std::vector<PairCoef> pp((size_t)B * kMaxTypes * kMaxTypes), pw(pp.size());
   memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
   memset(pw.data(), 0, pw.size() * sizeof(PairCoef));
   for (int b = 0; b < B; ++b) {
     Instance& I = c->inst[(size_t)b];
-    GridDev& g = I.grid;
-    int pos_of[3][32];
-    int next = 0;
-    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
-    for (int lvl = 0; lvl < maxb; ++lvl)
-      for (int a = 0; a < 3; ++a)
-        if (lvl < g.bits[a]) pos_of[a][lvl] = next++;
-    for (int a = 0; a < 3; ++a) {
-      g.mort[a] = d_mort + hmort.size();
-      for (int ci = 0; ci < g.nc[a]; ++ci) {
-        uint32_t key = 0;
-        for (int lvl = 0; lvl < g.bits[a]; ++lvl)
-          if ((ci >> lvl) & 1) key |= 1u << pos_of[a][lvl];
-        hmort.push_back(key);
-      }
-    }
-    InstDev& D = hinst[(size_t)b];
-    D.grid = g;
-    D.key_base = I.key_base;
-    D.wall_begin = I.w_begin;
-    D.wall_end = I.w_begin + (int)I.walls.size();
-    D.coef_base = b * kMaxTypes * kMaxTypes;
-    D.rs2 = I.rs * I.rs;
-    D.guard2 = (0.5 * I.skin) * (0.5 * I.skin);
-    D.skin = I.skin;
-    D.ihs = I.skin > 0.0 ? 2.0 / I.skin : 0.0;
+    const InstDev& D = hinst[(size_t)b];
     for (WallDev w : I.walls) {
       w.skin = I.skin;
       hwalls.push_back(w);
@@ -862,7 +967,7 @@ int commit(dem_ctx* c) {
   hipStream_t s = c->stream;
   if ((rc = wait_user(c))) return rc;
   if (!hmort.empty())
-    HIPCHK(hipMemcpyAsync(d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
+    HIPCHK(hipMemcpyAsync(c->d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
                         hipMemcpyHostToDevice, s));
@@ -933,6 +1038,9 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
     return set_err(DEM_EINVAL, "the linear model needs characteristic_velocity > 0");
   if (cfg->precision < 0 || cfg->precision > 1)
     return set_err(DEM_EINVAL, "precision must be 0 (FP64) or 1 (FP32 law)");
+  if (cfg->force_block != 0 && cfg->force_block != 64 && cfg->force_block != 128 &&
+      cfg->force_block != 256)
+    return set_err(DEM_EINVAL, "force_block must be 0, 64, 128 or 256");
   if (cfg->n_instances < 1 || cfg->n_instances > kMaxInstances)
     return set_err(DEM_EINVAL, "n_instances must be in [1, %d]", kMaxInstances);
   if (cfg->max_neighbors < 0 || cfg->max_neighbors > 4096)
@@ -948,6 +1056,7 @@ int dem_create(const dem_config* cfg, dem_ctx** out) {
                    prop.gcnArchName);
   dem_ctx* c = new dem_ctx();
   c->cfg = *cfg;
+  c->force_block = cfg->force_block ? cfg->force_block : kBlock;
   c->device = dev;
   c->inst.resize((size_t)cfg->n_instances);
   e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
@@ -1484,6 +1593,152 @@ int dem_get_stats(dem_ctx* c, dem_stats* out) {
 // Per-kernel timing for benchmarks: when enabled, dem_step launches eagerly
 // (no graphs) with HIP events around every force launch and every contact
 // search; dem_get_timing returns the accumulated milliseconds and counts.
+// Autotuner: every trial is a stretch of ordinary steps of the simulation
+// (or, for the cell size, forced re-sorts), so tuning advances the run with
+// unchanged physics; only summation orders differ between settings.
+int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
+  if (int rc = require_ready(c)) return rc;
+  if (!out) return set_err(DEM_EINVAL, "null argument");
+  if (trial_steps < 10 || trial_steps > 100000)
+    return set_err(DEM_EINVAL, "trial_steps must be in [10, 100000]");
+  if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
+  memset(out, 0, sizeof(*out));
+  for (int k = 0; k < 8; ++k) out->schedules[k] = -1;
+  if (c->n == 0) {
+    out->force_block = c->force_block;
+    out->rebuild_interval = c->cfg.rebuild_interval;
+    out->cell_factor = c->cell_factor;
+    return DEM_OK;
+  }
+  const bool timing0 = c->timing;
+  int64_t steps = 0;
+  int rc = DEM_OK;
+  auto forced_search = [&]() -> int {
+    int r = enqueue_rebuild(c, 0, 1);
+    if (r) return r;
+    int flags = 0;
+    if ((r = read_flags(c, &flags))) return r;
+    c->dyn_acc = 0.0;
+    return flags_to_error(c, flags);
+  };
+  auto run = [&](int64_t n) -> int {
+    steps += n;
+    return dem_step(c, n);
+  };
+  // 1. threads per force workgroup: force-kernel time from HIP events
+  const int blocks[3] = {64, 128, 256};
+  double best = HUGE_VAL;
+  int best_block = c->force_block;
+  for (int k = 0; k < 3; ++k) {
+    c->force_block = blocks[k];
+    destroy_graphs(c);
+    c->timing = true;
+    c->t_force_ms = c->t_search_ms = 0;
+    c->n_force = c->n_search = 0;
+    if ((rc = run(trial_steps))) break;
+    out->block_ms[k] = c->t_force_ms / (double)std::max<int64_t>(c->n_force, 1);
+    if (out->block_ms[k] < best) {
+      best = out->block_ms[k];
+      best_block = blocks[k];
+    }
+  }
+  c->timing = false;
+  c->force_block = best_block;
+  destroy_graphs(c);
+  if (rc) return rc;
+  // 2. cell edge: time of a forced contact search for h / d_max from r_s / d_max up
+  double f0 = HUGE_VAL;
+  for (const Instance& I : c->inst)
+    if (I.n > 0) f0 = std::min(f0, I.rs / I.dmax);
+  const double fmul[4] = {1.0, 1.15, 1.3, 1.5};
+  best = HUGE_VAL;
+  double best_cf = c->cell_factor;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (int k = 0; k < 4 && rc == DEM_OK; ++k) {
+    const double cf = f0 * fmul[k];
+    out->cell_factors[k] = cf;
+    if ((rc = regrid(c, cf))) break;
+    if ((rc = forced_search())) break;  // first search on new cells: untimed
+    float total = 0.f;
+    for (int r = 0; r < 3 && rc == DEM_OK; ++r) {
+      hipError_t he = hipEventRecord(e0, c->stream);
+      if (he == hipSuccess && (rc = enqueue_rebuild(c, 0, 1)) == DEM_OK) {
+        he = hipEventRecord(e1, c->stream);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        total += ms;
+      }
+      if (he != hipSuccess) rc = set_err(DEM_EHIP, "timing events: %s", hipGetErrorString(he));
+    }
+    out->search_ms[k] = total / 3.0;
+    if (rc == DEM_OK && out->search_ms[k] < best) {
+      best = out->search_ms[k];
+      best_cf = cf;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = regrid(c, best_cf))) return rc;
+  // 3. search schedule: whole steps per wall-clock time.  The dynamic trial
+  // runs first and measures the largest per-step drift; constant intervals
+  // are tried only while K drifts stay below a quarter of half the skin.
+  bool can_dynamic = true;
+  for (const Instance& I : c->inst)
+    if (I.n > 0 && !(I.skin > 0.0)) can_dynamic = false;
+  const int Ks[5] = {5, 10, 20, 40, 80};
+  int n_sched = 0;
+  // without a skin every displacement trips the guard: the schedule stays
+  if (can_dynamic) {
+    out->schedules[n_sched++] = 0;
+    for (int k = 0; k < 5; ++k) out->schedules[n_sched++] = Ks[k];
+  }
+  const int K0 = c->cfg.rebuild_interval;
+  best = HUGE_VAL;
+  int best_K = K0;
+  double rate = 0.0;  // largest per-step drift in half skins, from the dynamic trial
+  for (int k = 0; k < n_sched && rc == DEM_OK; ++k) {
+    const int K = out->schedules[k];
+    if (K > 0 && rate * K * 4.0 >= 1.0) {
+      out->schedule_ms[k] = -1.0;  // unsafe for the guard: not tried
+      continue;
+    }
+    c->cfg.rebuild_interval = K;
+    c->dynamic = K == 0;
+    destroy_graphs(c);
+    if ((rc = forced_search())) break;
+    const int64_t warm = K > 0 ? 2 * (int64_t)K : 2 * (int64_t)kDynChunk;
+    if ((rc = run(warm))) break;  // captures the graphs of this schedule
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((rc = run(trial_steps))) break;
+    const auto t1 = std::chrono::steady_clock::now();
+    out->schedule_ms[k] = std::chrono::duration<double, std::milli>(t1 - t0).count() / trial_steps;
+    if (K == 0) rate = c->dyn_rate;
+    if (out->schedule_ms[k] < best) {
+      best = out->schedule_ms[k];
+      best_K = K;
+    }
+  }
+  if (rc) return rc;
+  if (n_sched == 0) best = HUGE_VAL;
+  c->cfg.rebuild_interval = best_K;
+  c->dynamic = best_K == 0;
+  destroy_graphs(c);
+  if ((rc = forced_search())) return rc;
+  c->timing = timing0;
+  c->t_force_ms = c->t_search_ms = 0;
+  c->n_force = c->n_search = 0;
+  out->force_block = c->force_block;
+  out->rebuild_interval = best_K;
+  out->cell_factor = c->cell_factor;
+  out->ms_per_step = best;
+  out->steps = steps;
+  return DEM_OK;
+}
+
 int dem_set_timing(dem_ctx* c, int32_t enable) {
   if (!c) return set_err(DEM_EINVAL, "null context");
   c->timing = enable != 0;

@@ -158,7 +158,8 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, hipStream_t s);
+                        const int* flags, unsigned long long* drift, int block,
+                        hipStream_t s);
 // first half kick + drift from stored forces (start of a velocity-Verlet call).
 // When drift is not null, both launchers raise the kDriftSpread words at
 // drift (as the bits of non-negative doubles) so that their maximum is the

@@ -36,8 +36,8 @@ __device__ inline int xcd_block() {
   return (int)((b & 7u) * (nb >> 3) + (b >> 3));
 }
 
-static inline unsigned grid_for(int64_t n) {
-  int64_t b = (n + kBlock - 1) / kBlock;
+static inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t b = (n + block - 1) / block;
   if (b < 1) b = 1;
   b = (b + 7) & ~int64_t(7);
   return (unsigned)b;
@@ -783,26 +783,21 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
 constexpr int kTouchedBit = (int)0x80000000u;
 constexpr int kIndexMask = 0x7fffffff;
 
-// The states of a window of consecutive sorted particles, staged in LDS by
-// the block that covers the middle of the window: in spatial (Morton) order
-// most neighbours of a block's particles lie inside it, and they are then
-// read from LDS instead of through the cache hierarchy.
-#ifndef DEM_TILE_HALO
-#define DEM_TILE_HALO 0
-#endif
-constexpr int kTileHalo = DEM_TILE_HALO;
-constexpr int kTileSize = kBlock + 2 * kTileHalo;
-
+// The states of the BS consecutive sorted particles of a force block, staged
+// in LDS: in spatial (Morton) order most neighbours of a block's particles lie
+// inside the block, and they are then read from LDS instead of through the
+// cache hierarchy.
+template <int BS>
 struct Tile {
-  double4 p[kTileSize], v[kTileSize], w[kTileSize];
-  int in[kTileSize];
+  double4 p[BS], v[BS], w[BS];
+  int in[BS];
   int lo, hi;  // staged particles [lo, hi)
 
   __device__ __forceinline__ void stage(const ParticleBufs& src, const int* __restrict__ info,
                                         int first, int n) {
-    const int a = first < 0 ? 0 : first;
-    const int b = first + kTileSize < n ? first + kTileSize : n;
-    for (int t = threadIdx.x; t < b - a; t += kBlock) {
+    const int a = first;
+    const int b = first + BS < n ? first + BS : n;
+    for (int t = threadIdx.x; t < b - a; t += BS) {
       p[t] = src.pos[a + t];
       v[t] = src.vel[a + t];
       w[t] = src.omg[a + t];
@@ -844,14 +839,14 @@ __device__ __forceinline__ double drift_scale(const StepParams& sp,
 // Forces on particle i and its integration; returns the squared drift of
 // this step in units of half the instance's skin (for the dynamic search
 // trigger) when asked for it.
-template <typename R, int MODE, int MODEL>
+template <typename R, int MODE, int MODEL, typename TileT>
 __device__ __forceinline__ double force_particle(
     const int i, const StepParams& sp, const InstDev* __restrict__ inst,
     const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
     const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
     const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
     double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
-    const int* __restrict__ flags, const bool want_drift, const Tile& tile) {
+    const int* __restrict__ flags, const bool want_drift, const TileT& tile) {
   const int n = sp.n;
   double4 xi = tile.pos(in, i);
   double4 vi = tile.vel(in, i);
@@ -995,32 +990,34 @@ __device__ __forceinline__ double force_particle(
 
 // Largest value of a wavefront (shuffles), then one atomic per wavefront on
 // one of kDriftSpread words: non-negative doubles order like their bit
-// patterns.  Every lane of the wavefront calls it.
-__device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v) {
+// patterns.  Every lane of the wavefront calls it; waves_per_block is the
+// block size in wavefronts.
+__device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v,
+                                            int waves_per_block = kBlock / 64) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  const int w = (blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) & (kDriftSpread - 1);
+  const int w = (blockIdx.x * waves_per_block + (threadIdx.x >> 6)) & (kDriftSpread - 1);
   if ((threadIdx.x & 63) == 0 && v > 0.0)
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
 }
 
-template <typename R, int MODE, int MODEL>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+template <typename R, int MODE, int MODEL, int BS>
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
         const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
         ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
         double4* __restrict__ Fo, double4* __restrict__ To, const int64_t* __restrict__ clock,
         int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift) {
-  const int b0 = xcd_block() * kBlock;
+  const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
-  __shared__ Tile tile;
-  tile.stage(in, info, b0 - kTileHalo, sp.n);
+  __shared__ Tile<BS> tile;
+  tile.stage(in, info, b0, sp.n);
   __syncthreads();
   double d = 0.0;
   if (i < sp.n)
-    d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo, To,
-                                clock, step_rel, flags, drift != nullptr, tile);
-  if (drift) wave_max_to(drift, d);
+    d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
+                                       To, clock, step_rel, flags, drift != nullptr, tile);
+  if (drift) wave_max_to(drift, d, BS / 64);
 }
 
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
@@ -1028,17 +1025,28 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, hipStream_t s) {
+                        const int* flags, unsigned long long* drift, int block,
+                        hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  dim3 gr(grid_for(sp.n)), bl(kBlock);
-#define DEM_LAUNCH(RT, M, L)                                                                \
-  hipLaunchKernelGGL((k_force<RT, M, L>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, out, info, \
-                     l, ws, F, T, clock, step_rel, flags, drift)
-#define DEM_LAUNCH_MODE(RT, L)              \
-  do {                                      \
-    if (mode == 0) DEM_LAUNCH(RT, 0, L);    \
+  if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
+  dim3 gr(grid_for(sp.n, block)), bl(block);
+#define DEM_LAUNCH(RT, M, L)                                                                  \
+  do {                                                                                        \
+    if (block == 64)                                                                          \
+      hipLaunchKernelGGL((k_force<RT, M, L, 64>), gr, bl, 0, s, sp, inst, pp, pw, walls, in,  \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+    else if (block == 128)                                                                    \
+      hipLaunchKernelGGL((k_force<RT, M, L, 128>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_force<RT, M, L, 256>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+  } while (0)
+#define DEM_LAUNCH_MODE(RT, L)                \
+  do {                                        \
+    if (mode == 0) DEM_LAUNCH(RT, 0, L);      \
     else if (mode == 1) DEM_LAUNCH(RT, 1, L); \
-    else DEM_LAUNCH(RT, 2, L);              \
+    else DEM_LAUNCH(RT, 2, L);                \
   } while (0)
   if (precision == 0) {
     if (sp.model == 0) DEM_LAUNCH_MODE(double, 0);

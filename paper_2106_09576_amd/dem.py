@@ -33,6 +33,14 @@ class dem_material(C.Structure):
                 ("rolling_friction", C.c_double)]
 
 
+class dem_tuning(C.Structure):
+    _fields_ = [("force_block", C.c_int32), ("rebuild_interval", C.c_int32),
+                ("cell_factor", C.c_double), ("ms_per_step", C.c_double),
+                ("steps", C.c_int64), ("block_ms", C.c_double * 3),
+                ("cell_factors", C.c_double * 4), ("search_ms", C.c_double * 4),
+                ("schedules", C.c_int32 * 8), ("schedule_ms", C.c_double * 8)]
+
+
 class dem_config(C.Structure):
     _fields_ = [("dt", C.c_double), ("gravity", C.c_double * 3),
                 ("domain_lo", C.c_double * 3), ("domain_hi", C.c_double * 3),
@@ -41,7 +49,8 @@ class dem_config(C.Structure):
                 ("rolling_model", C.c_int32), ("precision", C.c_int32),
                 ("n_instances", C.c_int32), ("max_neighbors", C.c_int32),
                 ("hip_stream", C.c_void_p), ("contact_model", C.c_int32),
-                ("reserved", C.c_int32), ("characteristic_velocity", C.c_double)]
+                ("reserved", C.c_int32), ("characteristic_velocity", C.c_double),
+                ("force_block", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class dem_stats(C.Structure):
@@ -96,6 +105,7 @@ SIGNATURES = {
     "dem_get_stats": (C.c_int, [P, C.POINTER(dem_stats)]),
     "dem_stream": (C.c_void_p, [P]),
     "dem_set_timing": (C.c_int, [P, C.c_int32]),
+    "dem_autotune": (C.c_int, [P, C.c_int32, C.POINTER(dem_tuning)]),
     "dem_get_timing": (C.c_int, [P, DP]),
 }
 
@@ -136,7 +146,7 @@ class Dem:
                  neighbor_threshold=1.3, cell_factor=None, rebuild_interval=20,
                  integrator="verlet", rolling_model="constant", precision="fp64",
                  max_neighbors=0, hip_stream=None, n_instances=1, contact_model="nonlinear",
-                 characteristic_velocity=0.0):
+                 characteristic_velocity=0.0, force_block=0):
         self._lib = load_library()
         cfg = dem_config()
         cfg.dt = dt
@@ -150,6 +160,7 @@ class Dem:
         cfg.rolling_model = {"none": 0, "constant": 1, "viscous": 2}[rolling_model]
         cfg.contact_model = {"nonlinear": 0, "linear": 1}[contact_model]
         cfg.characteristic_velocity = characteristic_velocity
+        cfg.force_block = force_block
         cfg.precision = {"fp64": 0, "fp32": 1}[precision]
         cfg.n_instances = n_instances
         cfg.max_neighbors = max_neighbors
@@ -296,6 +307,18 @@ class Dem:
     def stream(self):
         return self._lib.dem_stream(self._h)
 
+    def autotune(self, trial_steps=200):
+        """Tune force block size, cell edge and search schedule on the running
+        simulation (advances it by the trial steps); returns the report."""
+        t = dem_tuning()
+        self._check(self._lib.dem_autotune(self._h, trial_steps, C.byref(t)))
+        sched = [int(k) for k in t.schedules if k >= 0]
+        return {"force_block": t.force_block, "rebuild_interval": t.rebuild_interval,
+                "cell_factor": t.cell_factor, "ms_per_step": t.ms_per_step, "steps": t.steps,
+                "block_ms": dict(zip((64, 128, 256), list(t.block_ms))),
+                "search_ms": dict(zip(list(t.cell_factors), list(t.search_ms))),
+                "schedule_ms": dict(zip(sched, list(t.schedule_ms)[:len(sched)]))}
+
     def set_timing(self, enable=True):
         self._check(self._lib.dem_set_timing(self._h, 1 if enable else 0))
 
@@ -335,12 +358,14 @@ class Dem:
                            instance=instance)
 
     @classmethod
-    def from_scene(cls, scene, precision="fp64", max_neighbors=0, hip_stream=None):
+    def from_scene(cls, scene, precision="fp64", max_neighbors=0, hip_stream=None,
+                   force_block=0):
         """Build a context from a scene dictionary (see ``workloads``)."""
-        return cls.from_scenes([scene], precision, max_neighbors, hip_stream)
+        return cls.from_scenes([scene], precision, max_neighbors, hip_stream, force_block)
 
     @classmethod
-    def from_scenes(cls, scenes, precision="fp64", max_neighbors=0, hip_stream=None):
+    def from_scenes(cls, scenes, precision="fp64", max_neighbors=0, hip_stream=None,
+                    force_block=0):
         """Build one batched context holding one instance per scene.  The scenes
         must share dt, gravity, search settings and integrator; each keeps its
         own domain box."""
@@ -357,7 +382,8 @@ class Dem:
                   integrator=c["integrator"], rolling_model=c["rolling_model"],
                   precision=precision, max_neighbors=max_neighbors, hip_stream=hip_stream,
                   n_instances=len(scenes), contact_model=c.get("contact_model", "nonlinear"),
-                  characteristic_velocity=c.get("characteristic_velocity", 0.0))
+                  characteristic_velocity=c.get("characteristic_velocity", 0.0),
+                  force_block=force_block)
         for k, s in enumerate(scenes):
             sim._add_scene(s, k, own_domain=len(scenes) > 1)
         if len(scenes) > 1:
