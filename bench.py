@@ -61,7 +61,7 @@ def load_traffic(precision):
     return None if e is None else float(e)
 
 
-def measure(args, precision, scene, label=None):
+def measure(args, precision, scene, label=None, autotune=False):
     import torch
     from paper_2106_09576_amd import Dem
 
@@ -77,6 +77,12 @@ def measure(args, precision, scene, label=None):
         sim.step(k)
         done += k
         log(f"{precision}: warmup {done}/{args.warmup}")
+    tune = None
+    if autotune:
+        tune = sim.autotune(trial_steps=args.tune_steps)
+        log(f"{precision}: autotuned block {tune['force_block']}, cell factor "
+            f"{tune['cell_factor']:.3f}, schedule {tune['rebuild_interval']} "
+            f"({tune['steps']} trial steps)")
     torch.cuda.synchronize()
     st0 = sim.get_stats()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -122,6 +128,7 @@ def measure(args, precision, scene, label=None):
         rebuilds_timed=int(st1["n_rebuilds"] - st0["n_rebuilds"]),
         device_gib=st1["device_bytes"] / 2 ** 30,
         max_neighbors=st1["max_neighbors"],
+        autotune=tune,
     )
     log(f"{precision}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step, "
         f"force kernel {force_ms:.4f} ms ({achieved:.0f} GB/s algorithmic)")
@@ -131,7 +138,9 @@ def measure(args, precision, scene, label=None):
 
 def measure_batched(args, precision):
     """The batched workload: 256 independent drums of uneven size (2k-50k
-    spheres, log-uniform) advanced together by every launch."""
+    spheres, log-uniform) advanced together by every launch, with the force
+    block size, cell edge and search schedule picked by the autotuner at the
+    end of the settling phase."""
     import torch
     import workloads as W
     from paper_2106_09576_amd import Dem
@@ -146,6 +155,12 @@ def measure_batched(args, precision):
         sim.step(k)
         done += k
         log(f"batched {precision}: warmup {done}/{args.batch_warmup}")
+    tune = None
+    if not args.no_autotune:
+        tune = sim.autotune(trial_steps=args.tune_steps)
+        log(f"batched {precision}: autotuned block {tune['force_block']}, cell factor "
+            f"{tune['cell_factor']:.3f}, schedule {tune['rebuild_interval']} "
+            f"({tune['steps']} trial steps)")
     st0 = sim.get_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -156,7 +171,7 @@ def measure_batched(args, precision):
     n_active = 0.5 * (st0["n_active"] + st1["n_active"])
     touching = 0.25 * (st0["n_touching"] + st1["n_touching"])
     sim.close()
-    res = dict(precision=precision, instances=len(scenes), n_particles=n,
+    res = dict(precision=precision, instances=len(scenes), n_particles=n, autotune=tune,
                value=n_active * args.batch_steps / wall, ms_per_step=1e3 * wall / args.batch_steps,
                contacts_per_s=touching * args.batch_steps / wall,
                touching_per_particle=touching / max(n_active, 1))
@@ -194,6 +209,10 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-dynamic", action="store_true",
                     help="skip the drum run with the displacement-triggered search")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuned legs (drum) and autotuning of the batch")
+    ap.add_argument("--tune-steps", type=int, default=200,
+                    help="steps per autotuner trial")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-warmup", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -273,12 +292,21 @@ def main():
                         "moved half the skin (rebuild_interval = 0)",
             "results": dres,
         }
+    if not args.no_autotune:
+        tres = {p: measure(args, p, scene, label=f"{p} autotuned", autotune=True) for p in precs}
+        out["autotuned"] = {
+            "workload": "same drum; force block size, cell edge and search schedule picked by "
+                        "dem_autotune after the settling steps",
+            "results": tres,
+        }
     if not args.skip_batched:
         b = {p: measure_batched(args, p) for p in precs}
         out["batched"] = {
             "workload": ("256 independent rotating drums in one context, 2k-50k spheres each "
                          "(log-uniform), d=3mm, mu U[0.1,0.5], 0.5-3 rad/s, 35% fill, dt=5e-6 s, "
-                         f"search every 20 steps, after {args.batch_warmup} settling steps"),
+                         f"after {args.batch_warmup} settling steps; "
+                         + ("autotuned block size, cell edge and search schedule"
+                            if not args.no_autotune else "search every 20 steps")),
             "results": b,
         }
         if "fp32" in b and "fp64" in b:
