@@ -227,6 +227,25 @@ int dem_get_state(dem_ctx* ctx, int32_t instance, double* pos, double* vel, doub
 int dem_get_state_device(dem_ctx* ctx, int32_t instance, double* pos, double* vel,
                          double* omega, uint8_t* active);
 
+/* Exact resume: restore into a freshly set instance what dem_set_particles
+   does not carry, as read from the saved context (instance-local gids):
+   n_pairs particle pairs (n_pairs x 2, gid_i < gid_j) that touched at the
+   last force evaluation with their tangential overlap (n_pairs x 3, i -> j;
+   j -> i gets the exact negative), n_wall particle-wall contacts (gid, wall
+   id) with their overlaps, the force and torque of the last evaluation
+   (n x 3 each, input order; NULL keeps the current ones), and the step
+   count (-1 keeps it; it sets the time used by wall activity windows).  The
+   pairs and walls must be candidates of the current lists: true when the
+   positions were saved right after a contact search (a multiple of K under
+   the constant schedule), which is also when the resumed run repeats the
+   saved one bit for bit.  Histories of the instance not listed are zeroed.
+   Host arrays are read and copied; DEM_EINVAL for a pair or wall contact that
+   is not in the lists (nothing is changed on the device then). */
+int dem_restore(dem_ctx* ctx, int32_t instance, int64_t n_pairs, const int64_t* pairs,
+                const double* delta_t, int64_t n_wall, const int64_t* wall_pairs,
+                const double* wall_delta_t, const double* force, const double* torque,
+                int64_t step);
+
 /* Total contact force and torque on every particle from the last force
    evaluation of the last dem_step call (zero before the first step). */
 int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque);

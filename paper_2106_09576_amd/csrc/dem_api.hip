@@ -1496,6 +1496,120 @@ int dem_get_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs, 
   return DEM_OK;
 }
 
+int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pairs,
+                const double* delta_t, int64_t n_wall, const int64_t* wall_pairs,
+                const double* wall_delta_t, const double* force, const double* torque,
+                int64_t step) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
+  if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
+  if (n_pairs < 0 || n_wall < 0) return set_err(DEM_EINVAL, "negative count");
+  if ((n_pairs > 0 && (!pairs || !delta_t)) || (n_wall > 0 && (!wall_pairs || !wall_delta_t)))
+    return set_err(DEM_EINVAL, "null array");
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  const int L = c->pcur;
+  const Instance& In = c->inst[(size_t)instance];
+  const int64_t base = In.p_begin;
+  std::vector<int> where((size_t)In.n, -1);  // instance gid -> sorted index
+  for (size_t p = 0; p < n; ++p)
+    if ((h.info[p] >> kInstShift) == instance) where[(size_t)(h.gid[p] - base)] = (int)p;
+  std::vector<int> rl(n), nb((size_t)c->cap);
+  std::vector<double> hs((size_t)c->cap * 3);
+  std::vector<int> w(n * kWallSlots);
+  std::vector<double> wh(n * kWallSlots * 3);
+  std::vector<double4> F(n), T(n);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(rl.data(), c->rowlen[L], n * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(nb.data(), c->nbr[L], (size_t)c->cap * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hs.data(), c->hist[L], (size_t)c->cap * 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(w.data(), c->wid[L], w.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(wh.data(), c->whist[L], wh.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(F.data(), c->F[L], n * sizeof(double4), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(T.data(), c->T[L], n * sizeof(double4), hipMemcpyDeviceToHost,
+                          c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  auto sorted = [&](int64_t g) -> int {
+    return g >= 0 && g < In.n ? where[(size_t)g] : -1;
+  };
+  // entries of this instance start without history, as after a search
+  for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    for (int k = 0; k < rl[p]; ++k) {
+      const size_t e = (size_t)nbr_entry((int)p, k, c->max_nb);
+      nb[e] &= 0x7fffffff;
+      hs[e] = hs[(size_t)c->cap + e] = hs[2 * (size_t)c->cap + e] = 0.0;
+    }
+  }
+  auto set_entry = [&](int p, int q, double sgn, const double* d) -> bool {
+    for (int k = 0; k < rl[(size_t)p]; ++k) {
+      const size_t e = (size_t)nbr_entry(p, k, c->max_nb);
+      if ((nb[e] & 0x7fffffff) != q) continue;
+      nb[e] = q | (int)0x80000000u;
+      for (int a = 0; a < 3; ++a) hs[(size_t)a * (size_t)c->cap + e] = sgn * d[a];
+      return true;
+    }
+    return false;
+  };
+  for (int64_t m = 0; m < n_pairs; ++m) {
+    const int p = sorted(pairs[2 * m]), q = sorted(pairs[2 * m + 1]);
+    if (p < 0 || q < 0 || p == q)
+      return set_err(DEM_EINVAL, "pair %lld: particle out of range", (long long)m);
+    // history of i -> j, and the exact negative from j's side
+    if (!set_entry(p, q, 1.0, delta_t + 3 * m) || !set_entry(q, p, -1.0, delta_t + 3 * m))
+      return set_err(DEM_EINVAL, "pair (%lld, %lld) is not in the contact list",
+                     (long long)pairs[2 * m], (long long)pairs[2 * m + 1]);
+  }
+  for (int64_t m = 0; m < n_wall; ++m) {
+    const int p = sorted(wall_pairs[2 * m]);
+    const int64_t wall = wall_pairs[2 * m + 1];
+    if (p < 0 || wall < 0 || wall >= (int64_t)In.walls.size())
+      return set_err(DEM_EINVAL, "wall contact %lld out of range", (long long)m);
+    bool found = false;
+    for (int sl = 0; sl < kWallSlots && !found; ++sl) {
+      if (w[(size_t)sl * n + (size_t)p] != In.w_begin + (int)wall) continue;
+      for (int a = 0; a < 3; ++a) wh[(size_t)(3 * sl + a) * n + (size_t)p] = wall_delta_t[3 * m + a];
+      found = true;
+    }
+    if (!found)
+      return set_err(DEM_EINVAL, "particle %lld is not a candidate of wall %lld",
+                     (long long)wall_pairs[2 * m], (long long)wall);
+  }
+  for (int64_t g = 0; g < In.n && (force || torque); ++g) {
+    const size_t p = (size_t)where[(size_t)g];
+    if (force) F[p] = make_double4(force[3 * g], force[3 * g + 1], force[3 * g + 2], 0.0);
+    if (torque) T[p] = make_double4(torque[3 * g], torque[3 * g + 1], torque[3 * g + 2], 0.0);
+  }
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(c->nbr[L], nb.data(), (size_t)c->cap * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->hist[L], hs.data(), (size_t)c->cap * 3 * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->whist[L], wh.data(), wh.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->F[L], F.data(), n * sizeof(double4), hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(c->T[L], T.data(), n * sizeof(double4), hipMemcpyHostToDevice,
+                          c->stream));
+  }
+  if (step >= 0) {
+    c->step = step;
+    c->host_base = step;
+    HIPCHK(hipMemcpyAsync(c->d_clock, &c->host_base, sizeof(int64_t), hipMemcpyHostToDevice,
+                          c->stream));
+  }
+  return finish(c);
+}
+
 int dem_get_wall_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
                           double* delta_t, int64_t* n_out) {
   if (int rc = require_ready(c)) return rc;

@@ -106,6 +106,8 @@ SIGNATURES = {
     "dem_stream": (C.c_void_p, [P]),
     "dem_set_timing": (C.c_int, [P, C.c_int32]),
     "dem_autotune": (C.c_int, [P, C.c_int32, C.POINTER(dem_tuning)]),
+    "dem_restore": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, C.c_int64, I64P, DP, DP, DP,
+                              C.c_int64]),
     "dem_get_timing": (C.c_int, [P, DP]),
 }
 
@@ -306,6 +308,32 @@ class Dem:
 
     def stream(self):
         return self._lib.dem_stream(self._h)
+
+    def checkpoint(self, instance=0):
+        """Everything an exact resume needs (see restore)."""
+        st = self.get_state(instance)
+        pairs, dt, touching = self.get_contacts(instance)
+        wpairs, wdt = self.get_wall_contacts(instance)
+        F, T = self.get_forces(instance)
+        t = touching.astype(bool)
+        return {"pos": st["pos"], "vel": st["vel"], "omega": st["omega"],
+                "pairs": pairs[t], "delta_t": dt[t], "wall_pairs": wpairs,
+                "wall_delta_t": wdt, "force": F, "torque": T,
+                "step": self.get_stats()["step"]}
+
+    def restore(self, ck, instance=0):
+        """Restore histories, forces and step count of a checkpoint into an
+        instance whose particles were set from the checkpoint's state."""
+        pairs = np.ascontiguousarray(ck["pairs"], dtype=np.int64).reshape(-1, 2)
+        dt = np.ascontiguousarray(ck["delta_t"], dtype=np.float64).reshape(-1, 3)
+        wp = np.ascontiguousarray(ck["wall_pairs"], dtype=np.int64).reshape(-1, 2)
+        wdt = np.ascontiguousarray(ck["wall_delta_t"], dtype=np.float64).reshape(-1, 3)
+        F = np.ascontiguousarray(ck["force"], dtype=np.float64)
+        T = np.ascontiguousarray(ck["torque"], dtype=np.float64)
+        self._check(self._lib.dem_restore(self._h, instance, pairs.shape[0],
+                                          pairs.ctypes.data_as(I64P), _d(dt), wp.shape[0],
+                                          wp.ctypes.data_as(I64P), _d(wdt), _d(F), _d(T),
+                                          int(ck["step"])))
 
     def autotune(self, trial_steps=200):
         """Tune force block size, cell edge and search schedule on the running
