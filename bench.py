@@ -225,6 +225,29 @@ def measure_small_box(args):
             "results": res, "fp32_law_vs_fp64": err}
 
 
+def copy_bandwidth():
+    """Achievable device bandwidth: five copies of 1 GiB (read 1 GiB, write
+    1 GiB each) timed with HIP events, after one untimed copy."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log(f"device copy: {gbs:.0f} GB/s")
+    return gbs
+
+
 def cpu_baseline(args, scene):
     """The FP64 oracle (plain C, single thread) on a bounded sample: the same
     1M-sphere drum from its initial state, a few steps including one search."""
@@ -296,6 +319,7 @@ def main():
     # force workgroups, cell edge = r_s
     main_scene = dict(scene, config=dict(scene["config"], rebuild_interval=0))
     results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK) for p in precs}
+    copy_gbs = copy_bandwidth()
     main_p = "fp64" if "fp64" in results else precs[0]
     r = results[main_p]
     traffic = load_traffic(main_p)
@@ -332,6 +356,8 @@ def main():
             "traffic": traffic,
             "force_kernel_ms": r["force_kernel_ms"],
             "algo_bytes_per_launch": r["force_kernel_algo_bytes"],
+            "copy_gbs": copy_gbs,
+            "frac_of_copy": r["force_kernel_gbs"] / copy_gbs,
         },
         "contacts_per_s": r["contacts_per_s"],
         "results": results,

@@ -444,12 +444,37 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
 // was touching (bit 31) names its partner by old index; inv maps it to the new
 // index, which is looked up in the new row.  Entries without bit 31 have zero
 // history, which is therefore never stored.
+// Positions of the search block's own sorted particles, staged in LDS: the
+// cells around a block's particles hold many of the block's particles (a
+// window with a halo of further sorted neighbours measured slower, its LDS
+// footprint lowering occupancy).
+struct SearchTile {
+  double4 p[kBlock];
+  int lo, hi;  // staged particles [lo, hi)
+  __device__ __forceinline__ void stage(const double4* __restrict__ pos, int first, int n) {
+    const int a = first;
+    const int b = first + kBlock < n ? first + kBlock : n;
+    for (int t = threadIdx.x; t < b - a; t += kBlock) p[t] = pos[a + t];
+    if (threadIdx.x == 0) {
+      lo = a;
+      hi = b > a ? b : a;
+    }
+  }
+  __device__ __forceinline__ double4 get(const double4* __restrict__ pos, int q) const {
+    return (q >= lo && q < hi) ? p[q - lo] : pos[q];
+  }
+};
+
 __global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
                          const double4* __restrict__ pos,
                          const int* __restrict__ info, const int* __restrict__ start,
                          const int* __restrict__ perm, const int* __restrict__ inv,
                          NbrList old_l, NbrList new_l, int* __restrict__ flags) {
-  int p = xcd_block() * kBlock + threadIdx.x;
+  const int b0 = xcd_block() * kBlock;
+  int p = b0 + threadIdx.x;
+  __shared__ SearchTile tile;
+  tile.stage(pos, b0, sp.n);
+  __syncthreads();
   if (p >= sp.n) return;
   const int max_nb = sp.max_nb;
   const int inf = info[p];
@@ -482,7 +507,7 @@ __global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
         const int s = start[key], e = start[key + 1];
         for (int q = s; q < e; ++q) {
           if (q == p) continue;
-          const double4 pq = pos[q];
+          const double4 pq = tile.get(pos, q);
           const double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
           const double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
           if (!(d2 < rs2)) continue;
