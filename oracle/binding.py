@@ -74,6 +74,7 @@ def _load():
                                      C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_int32)]
         lib.ora_step.argtypes = [P, C.c_int64]
+        lib.ora_set_wall_velocity.argtypes = [P, C.c_int32, D]
         lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
         lib.ora_get_forces.argtypes = [P, D, D]
         lib.ora_get_force_scale.argtypes = [P, D]
@@ -184,6 +185,10 @@ class OracleSim:
                                       1 if inside else 0, material, omega, t_on, t_off,
                                       C.byref(wid)), "ora_add_cone")
         return wid.value
+
+    def set_wall_velocity(self, wall_id, vel):
+        v = _vec(vel)
+        _check(self._lib.ora_set_wall_velocity(self._h, wall_id, _dp(v)), "ora_set_wall_velocity")
 
     def set_particles(self, pos, radius, vel=None, omega=None, types=None):
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
@@ -300,6 +305,9 @@ def oracle_from_scene(scene: dict) -> OracleSim:
             sim.add_cone(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"], w["s_min"],
                          w["s_max"], w["inside"], w["material"], w["omega"], w["t_on"],
                          w["t_off"])
+    for k, w in enumerate(scene["walls"]):
+        if w.get("velocity") is not None:
+            sim.set_wall_velocity(k, w["velocity"])
     p = scene["particles"]
     sim.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"])
     return sim

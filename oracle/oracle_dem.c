@@ -27,7 +27,8 @@
  *   Sec. 3.2                       broad search over cells and their neighbour
  *             cells listed without repetition, then a fine search that keeps
  *             pairs closer than a threshold; Sec. 3.1: searched every n steps
- *   Sec. 3.7                       moving (rotating) and floating walls
+ *   Sec. 3.7                       moving (rotating and translating) and floating
+ *                                  walls
  *   walls are analytic surfaces (plane, cylinder, cone) standing in for the
  *   paper's meshed boundaries
  *
@@ -79,7 +80,18 @@ typedef struct {
   double omega[3]; /* angular velocity vector of the wall */
   double ax[3];    /* a point on the rotation axis */
   double t_on, t_off;
+  double vel[3];   /* translational velocity: p and ax move with it */
 } ora_wall;
+
+/* The wall at time t: its point and rotation axis translated by vel t. */
+static ora_wall wall_at(const ora_wall* W, double t) {
+  ora_wall out = *W;
+  for (int k = 0; k < 3; ++k) {
+    out.p[k] = W->p[k] + W->vel[k] * t;
+    out.ax[k] = W->ax[k] + W->vel[k] * t;
+  }
+  return out;
+}
 
 typedef struct {
   int64_t i, j; /* gid_i < gid_j */
@@ -426,6 +438,8 @@ static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const doubl
                       double* delta_t, double* Fi, double* Mi, double* fmag) {
   for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = 0.0;
   *fmag = 0.0;
+  const ora_wall Wt = wall_at(W, t);
+  W = &Wt;
   ora_wgeo g;
   wall_geometry(W, x, R, s->skin, &g);
   if (!wall_enabled(W, t) || !g.touching) {
@@ -433,10 +447,12 @@ static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const doubl
     return 0;
   }
   double dn = g.dn < 0.0 ? 0.0 : g.dn;
-  /* velocity of the wall surface at the contact point: Omega x (x_c - axis point) */
+  /* velocity of the wall surface at the contact point:
+     v_wall + Omega x (x_c - axis point) */
   double arm[3], vw[3];
   vsub(g.xc, W->ax, arm);
   vcross(W->omega, arm, vw);
+  for (int k = 0; k < 3; ++k) vw[k] = W->vel[k] + vw[k];
   double rw[3] = {R * w[0], R * w[1], R * w[2]};
   double rwxn[3];
   vcross(rw, g.n, rwxn);
@@ -640,11 +656,13 @@ static int rebuild(ora_sim* s) {
   ora_wpair* W = (ora_wpair*)malloc(sizeof(ora_wpair) * (size_t)cap);
   if (!W) return ORA_ENOMEM;
   int64_t old = 0;
+  const double t_search = (double)s->step * s->cfg.dt; /* walls where they are now */
   for (int64_t i = 0; i < s->n; ++i) {
     if (!s->active[i]) continue;
     for (int w = 0; w < s->nw; ++w) {
       ora_wgeo g;
-      wall_geometry(&s->walls[w], &s->x[3 * i], s->R[i], s->skin, &g);
+      const ora_wall Wt = wall_at(&s->walls[w], t_search);
+      wall_geometry(&Wt, &s->x[3 * i], s->R[i], s->skin, &g);
       if (!g.candidate) continue;
       if (cnt == cap) {
         cap *= 2;
@@ -866,6 +884,13 @@ int ora_set_particles(ora_sim* s, int64_t n, const double* pos, const double* ve
     int64_t c = (int64_t)ceil(span / (s->h > 0.0 ? s->h : 1.0));
     s->nc[k] = c < 1 ? 1 : c;
   }
+  /* a moving wall may travel at most half the skin between two searches:
+     with the particles' half skin, no contact is missed */
+  for (int w = 0; w < s->nw; ++w) {
+    double vw = vnorm(s->walls[w].vel);
+    if (vw > 0.0 && !(vw * (double)s->cfg.rebuild_interval * s->cfg.dt <= 0.5 * s->skin))
+      return ORA_EINVAL;
+  }
   s->step = 0;
   s->ready = 0;
   int rc = rebuild(s);
@@ -975,6 +1000,16 @@ int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3
   s->walls[s->nw] = W;
   if (wall_id) *wall_id = s->nw;
   s->nw += 1;
+  return ORA_OK;
+}
+
+int ora_set_wall_velocity(ora_sim* s, int32_t wall_id, const double vel[3]) {
+  if (!s || !vel || wall_id < 0 || wall_id >= s->nw) return ORA_EINVAL;
+  if (s->n > 0) return ORA_ESTATE;
+  for (int k = 0; k < 3; ++k) {
+    if (!isfinite(vel[k])) return ORA_EINVAL;
+    s->walls[wall_id].vel[k] = vel[k];
+  }
   return ORA_OK;
 }
 

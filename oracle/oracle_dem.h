@@ -70,6 +70,9 @@ int ora_add_cylinder(ora_sim* s, const double axis_point[3], const double axis_d
 int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3],
                  double radius0, double slope, double s_min, double s_max, int32_t inside,
                  int32_t material, double omega, double t_on, double t_off, int32_t* wall_id);
+/* Constant translational velocity of a wall (before the particles are set):
+   its point and rotation axis move with it. */
+int ora_set_wall_velocity(ora_sim* s, int32_t wall_id, const double vel[3]);
 int ora_step(ora_sim* s, int64_t n_steps);
 int ora_get_state(ora_sim* s, double* pos, double* vel, double* omega, uint8_t* active,
                   double* time_out);
