@@ -175,6 +175,22 @@ int dem_add_cone_wall(dem_ctx* ctx, int32_t instance, const double axis_point[3]
                       double s_max, int32_t inside, int32_t material, double omega, double t_on,
                       double t_off, int32_t* wall_id);
 
+/* Translational motion of wall `wall_id` of an instance (Sec. 3.7, boundary
+   motion: boundaries may rotate or translate): the wall moves with constant
+   velocity `velocity` (3 doubles, m/s), so that at time t its point and its
+   rotation axis lie at their given positions + velocity t, and the velocity
+   of its surface at a contact point x_c is velocity + Omega x (x_c - axis(t)).
+   Every contact search places the walls where they are at the step it runs
+   at.  Between two searches a translating wall may move at most half the
+   skin (r_s - d_max): |velocity| K dt <= skin / 2 for rebuild_interval K, or
+   |velocity| dt <= skin / 2 with the dynamic schedule, which then also
+   searches before any wall has covered half the skin since the last search;
+   the call that builds the batch returns DEM_EINVAL otherwise.  Called
+   before dem_set_particles for that instance (else DEM_ESTATE); DEM_EINVAL
+   for an unknown wall id or a non-finite velocity.  The default is 0. */
+int dem_set_wall_motion(dem_ctx* ctx, int32_t instance, int32_t wall_id,
+                        const double velocity[3]);
+
 /* Set n >= 0 particles of one instance: positions (n x 3), velocities and
    angular velocities (n x 3, NULL = zero), radii (n, > 0) and material types
    (n, NULL = type 0; each type's material must be set).  Masses are

@@ -123,6 +123,8 @@ struct dem_ctx {
   double dyn_acc = 0.0;
   double dyn_rate = 0.0;
   double dyn_grav = 0.0;  // |g| dt^2 (2/skin)max: growth of the rate per step
+  double dyn_wrate = 0.0;  // largest step of a translating wall, in half skins
+  double dyn_wacc = 0.0;   // distance walls moved since the last search, in half skins
   hipGraphExec_t dyn_graph[2][2][2]{};  // [cur][pcur][chunk starts with a search]
 
   // optional per-kernel timing (benchmarks): events around force launches
@@ -276,8 +278,9 @@ NbrList nlist(dem_ctx* c, int k) { return NbrList{c->nbr[k], c->hist[k], c->rowl
 WallSlots wslots(dem_ctx* c, int k) { return WallSlots{c->wid[k], c->whist[k]}; }
 
 // Contact search: counting sort into cells, reorder, particle-wall search and
-// particle-pair search with history carry-over.  Flips both parities.
-int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
+// particle-pair search with history carry-over.  Flips both parities.  The
+// search takes place at time (clock + step_rel) dt, where moving walls are.
+int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_rel) {
   hipStream_t s = c->stream;
   const int a = c->cur, p = c->pcur;
   HIPCHK(launch_fill_i32(c->count, 0, c->n_keys + 1, s));
@@ -293,7 +296,7 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces) {
                         c->info[p], c->info[p ^ 1], c->xref, wslots(c, p), wslots(c, p ^ 1),
                         c->d_walls, move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
-                        c->d_flags, s));
+                        c->d_clock, step_rel, c->d_flags, s));
   HIPCHK(launch_search(c->d_inst, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
                        c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
@@ -355,10 +358,10 @@ int collect_timing(dem_ctx* c) {
 // stored forces move with the particles to stay readable by dem_get_forces.
 int move_forces_at_search(const dem_ctx* c) { return c->cfg.integrator == 1 ? 1 : 0; }
 
-int eager_rebuild(dem_ctx* c) {
+int eager_rebuild(dem_ctx* c, int64_t step_rel) {
   int rc = timed_begin(c, 1);
   if (rc) return rc;
-  rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
+  rc = enqueue_rebuild(c, 1, move_forces_at_search(c), step_rel);
   if (rc) return rc;
   return timed_end(c);
 }
@@ -392,11 +395,12 @@ int get_chunk_graph(dem_ctx* c, hipGraphExec_t* out) {
   HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   int rc = DEM_OK;
   if (c->cfg.integrator == 0) {
-    rc = enqueue_rebuild(c, 1, 0);
+    rc = enqueue_rebuild(c, 1, 0, 0);
     for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 0, j);
   } else {
+    // Euler: the search follows the K updates, at the time of the last
     for (int j = 0; j < K && rc == DEM_OK; ++j) rc = enqueue_force(c, 2, j);
-    if (rc == DEM_OK) rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
+    if (rc == DEM_OK) rc = enqueue_rebuild(c, 1, move_forces_at_search(c), K);
   }
   if (rc == DEM_OK) {
     hipError_t e = launch_tick(c->d_clock, K, c->stream);
@@ -454,7 +458,7 @@ int enqueue_dyn_chunk(dem_ctx* c, int L, bool search, bool last_is_call_end) {
   HIPCHK(launch_fill_i32((int*)(c->d_drift + kDriftSpread), 0, 2 * kDriftSpread * (int64_t)L,
                          c->stream));
   if (search) {
-    int rc = enqueue_rebuild(c, 1, move_forces_at_search(c));
+    int rc = enqueue_rebuild(c, 1, move_forces_at_search(c), 0);
     if (rc) return rc;
   }
   for (int j = 0; j < L; ++j) {
@@ -538,9 +542,14 @@ int step_dynamic(dem_ctx* c, int64_t n_steps) {
     // keep one chunk's worth of predicted drift below half a skin
     const double rate = c->dyn_rate + c->dyn_grav * L;
     while (L > 1 && 2.0 * L * rate >= 0.5) --L;
+    // translating walls cover at most half a skin between two searches
+    while (L > 1 && L * c->dyn_wrate > 1.0) --L;
     const double pred = 2.0 * L * (c->dyn_rate + c->dyn_grav * L);
-    const bool search = c->dyn_acc + pred >= 1.0;
-    if (search) c->dyn_acc = 0.0;
+    const bool search = c->dyn_acc + pred >= 1.0 || c->dyn_wacc + L * c->dyn_wrate > 1.0;
+    if (search) {
+      c->dyn_acc = 0.0;
+      c->dyn_wacc = 0.0;
+    }
     const bool call_end = s + L - 1 == s_end;
     if (graphs && L == kDynChunk && !call_end) {
       if ((rc = set_clock(c, s - (vv ? 0 : 1)))) return rc;
@@ -558,7 +567,7 @@ int step_dynamic(dem_ctx* c, int64_t n_steps) {
       const int64_t base = (vv ? s : s - 1) - c->host_base;
       HIPCHK(launch_fill_i32((int*)(c->d_drift + kDriftSpread), 0,
                              2 * kDriftSpread * (int64_t)L, c->stream));
-      if (search && (rc = eager_rebuild(c))) return rc;
+      if (search && (rc = eager_rebuild(c, base))) return rc;
       for (int j = 0; j < L; ++j) {
         const int mode = vv ? ((call_end && j == L - 1) ? 1 : 0) : 2;
         unsigned long long* rec = c->d_drift + (size_t)kDriftSpread * (1 + j);
@@ -567,6 +576,7 @@ int step_dynamic(dem_ctx* c, int64_t n_steps) {
     }
     // the last force launch of a Verlet call does not drift
     if ((rc = fold_drift(c, 1, vv && call_end ? L - 1 : L))) return rc;
+    c->dyn_wacc += L * c->dyn_wrate;
     s += L;
   }
   return DEM_OK;
@@ -631,6 +641,38 @@ int snapshot(dem_ctx* c, HostSnapshot& h, bool want_pos, bool want_vel, bool wan
 }
 
 int commit(dem_ctx* c);
+
+// Translating walls: a wall may move at most half the skin between two
+// searches, the particles' displacement guard taking the other half, so that
+// no particle-wall contact is missed.  walls_fit tells whether K steps of
+// every translating wall stay within that; wall_rate is the largest distance
+// one step of a translating wall covers, in half skins of its instance.
+double wall_speed(const WallDev& w) {
+  return sqrt((w.vel[0] * w.vel[0] + w.vel[1] * w.vel[1]) + w.vel[2] * w.vel[2]);
+}
+
+bool walls_fit(const dem_ctx* c, int64_t K) {
+  for (const Instance& I : c->inst) {
+    if (I.n == 0) continue;
+    for (const WallDev& w : I.walls) {
+      const double v = wall_speed(w);
+      if (v > 0.0 && !(v * (double)K * c->cfg.dt <= 0.5 * I.skin)) return false;
+    }
+  }
+  return true;
+}
+
+double wall_rate(const dem_ctx* c) {
+  double r = 0.0;
+  for (const Instance& I : c->inst) {
+    if (I.n == 0) continue;
+    for (const WallDev& w : I.walls) {
+      const double v = wall_speed(w);
+      if (v > 0.0) r = std::max(r, I.skin > 0.0 ? v * c->cfg.dt * 2.0 / I.skin : HUGE_VAL);
+    }
+  }
+  return r;
+}
 
 // Cell grid of every instance for the cell edge h = cf d_max (1 + 1e-9),
 // never below the search radius r_s: cell counts, Morton bit widths and one
@@ -838,9 +880,15 @@ int commit(dem_ctx* c) {
   const double gmag = sqrt((c->cfg.gravity[0] * c->cfg.gravity[0] +
                             c->cfg.gravity[1] * c->cfg.gravity[1]) +
                            c->cfg.gravity[2] * c->cfg.gravity[2]);
+  if (!walls_fit(c, c->dynamic ? 1 : c->cfg.rebuild_interval))
+    return set_err(DEM_EINVAL,
+                   "a translating wall moves more than half the skin between two contact "
+                   "searches; lower rebuild_interval or dt, or raise neighbor_threshold");
   c->dyn_acc = 0.0;
   c->dyn_rate = rate0;
   c->dyn_grav = gmag * c->cfg.dt * c->cfg.dt * ihs_max;
+  c->dyn_wrate = wall_rate(c);
+  c->dyn_wacc = 0.0;
   int max_nb = c->cfg.max_neighbors;
   if (max_nb == 0) max_nb = (int)std::min(512.0, ceil(bound_nb));
   c->max_nb = max_nb;
@@ -998,7 +1046,7 @@ int commit(dem_ctx* c) {
   c->step = 0;
   c->host_base = 0;
   c->n_rebuilds = 0;
-  if ((rc = enqueue_rebuild(c, 0, 0))) return rc;
+  if ((rc = enqueue_rebuild(c, 0, 0, 0))) return rc;
   int flags = 0;
   if ((rc = read_flags(c, &flags))) return rc;
   c->ready = true;
@@ -1205,6 +1253,20 @@ int dem_add_cone_wall(dem_ctx* c, int32_t instance, const double axis_point[3],
   return DEM_OK;
 }
 
+int dem_set_wall_motion(dem_ctx* c, int32_t instance, int32_t wall_id,
+                        const double velocity[3]) {
+  if (!c || !velocity) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if (wall_id < 0 || wall_id >= (int32_t)I.walls.size())
+    return set_err(DEM_EINVAL, "instance %d has no wall %d", instance, wall_id);
+  if (I.staged) return set_err(DEM_ESTATE, "wall motion is set before dem_set_particles");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(velocity[k])) return set_err(DEM_EINVAL, "non-finite wall velocity");
+  for (int k = 0; k < 3; ++k) I.walls[(size_t)wall_id].vel[k] = velocity[k];
+  return DEM_OK;
+}
+
 int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos,
                       const double* vel, const double* omega, const double* radius,
                       const int32_t* type) {
@@ -1326,7 +1388,7 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
         s += K;
         continue;
       }
-      if (s % K == 0 && (rc = eager_rebuild(c))) return rc;
+      if (s % K == 0 && (rc = eager_rebuild(c, s - c->host_base))) return rc;
       if ((rc = eager_force(c, s < s_end ? 0 : 1, s - c->host_base))) return rc;
       s += 1;
     }
@@ -1339,7 +1401,7 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
         continue;
       }
       if ((rc = eager_force(c, 2, (s - 1) - c->host_base))) return rc;
-      if (s % K == 0 && (rc = eager_rebuild(c))) return rc;
+      if (s % K == 0 && (rc = eager_rebuild(c, s - c->host_base))) return rc;
       s += 1;
     }
   }
@@ -1507,6 +1569,22 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
   if ((n_pairs > 0 && (!pairs || !delta_t)) || (n_wall > 0 && (!wall_pairs || !wall_delta_t)))
     return set_err(DEM_EINVAL, "null array");
   if (int rc = wait_user(c)) return rc;
+  if (step >= 0) {
+    c->step = step;
+    c->host_base = step;
+    HIPCHK(hipMemcpyAsync(c->d_clock, &c->host_base, sizeof(int64_t), hipMemcpyHostToDevice,
+                          c->stream));
+    // translating walls: search again with the walls where they are at the
+    // restored time (the lists were built with them elsewhere)
+    if (c->n > 0 && wall_rate(c) > 0.0) {
+      if (int rc = enqueue_rebuild(c, 0, 1, 0)) return rc;
+      c->dyn_acc = 0.0;
+      c->dyn_wacc = 0.0;
+      int flags = 0;
+      if (int rc = read_flags(c, &flags)) return rc;
+      if (int rc = flags_to_error(c, flags)) return rc;
+    }
+  }
   HostSnapshot h;
   if (int rc = snapshot(c, h, false, false, false)) return rc;
   const size_t n = (size_t)c->n;
@@ -1544,6 +1622,7 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
   // entries of this instance start without history, as after a search
   for (size_t p = 0; p < n; ++p) {
     if ((h.info[p] >> kInstShift) != instance) continue;
+    for (int a = 0; a < 3 * kWallSlots; ++a) wh[(size_t)a * n + p] = 0.0;
     for (int k = 0; k < rl[p]; ++k) {
       const size_t e = (size_t)nbr_entry((int)p, k, c->max_nb);
       nb[e] &= 0x7fffffff;
@@ -1599,12 +1678,6 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
     HIPCHK(hipMemcpyAsync(c->F[L], F.data(), n * sizeof(double4), hipMemcpyHostToDevice,
                           c->stream));
     HIPCHK(hipMemcpyAsync(c->T[L], T.data(), n * sizeof(double4), hipMemcpyHostToDevice,
-                          c->stream));
-  }
-  if (step >= 0) {
-    c->step = step;
-    c->host_base = step;
-    HIPCHK(hipMemcpyAsync(c->d_clock, &c->host_base, sizeof(int64_t), hipMemcpyHostToDevice,
                           c->stream));
   }
   return finish(c);
@@ -1666,7 +1739,9 @@ int dem_resort(dem_ctx* c) {
   if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
   if (int rc = wait_user(c)) return rc;
   if (c->n == 0) return DEM_OK;
-  if (int rc = enqueue_rebuild(c, 0, 1)) return rc;
+  if (int rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base)) return rc;
+  c->dyn_acc = 0.0;
+  c->dyn_wacc = 0.0;
   int flags = 0;
   if (int rc = read_flags(c, &flags)) return rc;
   return flags_to_error(c, flags);
@@ -1728,11 +1803,12 @@ int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
   int64_t steps = 0;
   int rc = DEM_OK;
   auto forced_search = [&]() -> int {
-    int r = enqueue_rebuild(c, 0, 1);
+    int r = enqueue_rebuild(c, 0, 1, c->step - c->host_base);
     if (r) return r;
     int flags = 0;
     if ((r = read_flags(c, &flags))) return r;
     c->dyn_acc = 0.0;
+    c->dyn_wacc = 0.0;
     return flags_to_error(c, flags);
   };
   auto run = [&](int64_t n) -> int {
@@ -1778,7 +1854,7 @@ int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
     float total = 0.f;
     for (int r = 0; r < 3 && rc == DEM_OK; ++r) {
       hipError_t he = hipEventRecord(e0, c->stream);
-      if (he == hipSuccess && (rc = enqueue_rebuild(c, 0, 1)) == DEM_OK) {
+      if (he == hipSuccess && (rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base)) == DEM_OK) {
         he = hipEventRecord(e1, c->stream);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;
@@ -1816,8 +1892,8 @@ int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
   double rate = 0.0;  // largest per-step drift in half skins, from the dynamic trial
   for (int k = 0; k < n_sched && rc == DEM_OK; ++k) {
     const int K = out->schedules[k];
-    if (K > 0 && rate * K * 4.0 >= 1.0) {
-      out->schedule_ms[k] = -1.0;  // unsafe for the guard: not tried
+    if (K > 0 && (rate * K * 4.0 >= 1.0 || !walls_fit(c, K))) {
+      out->schedule_ms[k] = -1.0;  // unsafe for the guard or a moving wall: not tried
       continue;
     }
     c->cfg.rebuild_interval = K;

@@ -43,8 +43,9 @@ struct PairCoef {
 // optional rectangular extent along u / vax).  kind 2: cone, as the cylinder
 // with the surface at radius + slope s.  kind 1: cylinder (axis point p,
 // unit axis nrm, radius, axial range [smin, smax], particles inside or
-// outside).  Rotation: surface velocity omega x (x_c - ax).  Active for
-// t_on <= t < t_off.
+// outside).  Translation with velocity vel: at time t the point and the
+// rotation axis sit at p + vel t and ax + vel t.  Surface velocity at a
+// contact point x_c: vel + omega x (x_c - ax(t)).  Active for t_on <= t < t_off.
 struct WallDev {
   int kind, bounded, inside, material;
   double p[3], nrm[3], u[3], vax[3];
@@ -53,6 +54,7 @@ struct WallDev {
   double t_on, t_off;
   double skin;  // the owning instance's skin (contact-search margin)
   double slope, q;  // cone: radius + slope s at axial coordinate s; q = sqrt(1 + slope^2)
+  double vel[3];
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).
@@ -138,13 +140,16 @@ hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const in
 hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
                             const int* start, const int* gid, int* perm, hipStream_t s);
 // perm: new -> old index; inv receives old -> new
+// The particle-wall search takes the walls where they are at time
+// (*clock + step_rel) dt.
 hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
                           ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
-                          double4* T_dst, int* flags, hipStream_t s);
+                          double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
+                          hipStream_t s);
 hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double4* pos,
                          const int* info, const int* start, const int* perm, const int* inv,
                          NbrList old_l, NbrList new_l, int* flags, hipStream_t s);

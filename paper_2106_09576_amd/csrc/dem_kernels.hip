@@ -256,8 +256,8 @@ hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint3
 // ------------------------------------------------------------------ walls
 
 // Candidate / touching predicates of particle centre x (radius R) against a
-// wall, evaluated without square roots; when touching also the unit normal
-// from the particle to the wall, the overlap and the contact point.
+// wall at time t, evaluated without square roots; when touching also the unit
+// normal from the particle to the wall, the overlap and the contact point.
 struct WallGeo {
   bool candidate, touching;
   double n[3], dn, xc[3];
@@ -268,10 +268,11 @@ __device__ inline double dot3(const double* a, const double* b) {
 }
 
 __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, double skin,
-                                bool need_contact, WallGeo& g) {
+                                bool need_contact, double t, WallGeo& g) {
   g.candidate = false;
   g.touching = false;
-  double rel[3] = {x[0] - W.p[0], x[1] - W.p[1], x[2] - W.p[2]};
+  const double P[3] = {W.p[0] + W.vel[0] * t, W.p[1] + W.vel[1] * t, W.p[2] + W.vel[2] * t};
+  double rel[3] = {x[0] - P[0], x[1] - P[1], x[2] - P[2]};
   if (W.kind == 0) {
     double dist = dot3(rel, W.nrm);
     if (W.bounded) {
@@ -350,7 +351,7 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
     g.dn = R - dist;
     for (int k = 0; k < 3; ++k) {
       g.n[k] = W.inside ? er[k] : -er[k];
-      g.xc[k] = W.p[k] + sax * W.nrm[k] + Rc * er[k];
+      g.xc[k] = P[k] + sax * W.nrm[k] + Rc * er[k];
     }
   }
 }
@@ -368,10 +369,12 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* __restrict__ walls,
                           const double4* __restrict__ F_src, const double4* __restrict__ T_src,
                           double4* __restrict__ F_dst, double4* __restrict__ T_dst,
+                          const int64_t* __restrict__ clock, int64_t step_rel,
                           int* __restrict__ flags) {
   int p = xcd_block() * kBlock + threadIdx.x;
   const int n = sp.n;
   if (p >= n) return;
+  const double t = (double)(*clock + step_rel) * sp.dt;  // walls where they are now
   int o = perm[p];
   inv[o] = p;
   double4 ps = src.pos[o];
@@ -392,7 +395,7 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
     double x[3] = {ps.x, ps.y, ps.z};
     for (int w = I.wall_begin; w < I.wall_end; ++w) {
       WallGeo g;
-      wall_geo(walls[w], x, ps.w, I.skin, false, g);
+      wall_geo(walls[w], x, ps.w, I.skin, false, t, g);
       if (!g.candidate) continue;
       if (c == kWallSlots) {
         atomicOr(flags, kFlagWallOverflow);
@@ -424,12 +427,13 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           const double4* F_src, const double4* T_src, double4* F_dst,
-                          double4* T_dst, int* flags, hipStream_t s) {
+                          double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
+                          hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, perm, inv,
                      src, dst,
                      gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, F_src,
-                     T_src, F_dst, T_dst, flags);
+                     T_src, F_dst, T_dst, clock, step_rel, flags);
   return hipGetLastError();
 }
 
@@ -755,16 +759,16 @@ __device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling
   hm_law<float>(c, rolling, model, dt, dn, n, vij, wrel, vr, me, Re, Ri, dtl, Fi, Mi);
 }
 
-// Particle against wall W, the wall acting as a body of infinite mass and
-// radius whose contact point moves with the wall's surface velocity.
+// Particle against wall W at time t, the wall acting as a body of infinite
+// mass and radius whose contact point moves with the wall's surface velocity.
 template <typename R>
 __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int model, double dt,
-                                           const WallDev& W, double skin, double4 xi,
+                                           const WallDev& W, double skin, double t, double4 xi,
                                            double4 vi, double4 wi, double dtl[3],
                                            double Fi[3], double Mi[3]) {
   const double x[3] = {xi.x, xi.y, xi.z};
   WallGeo g;
-  wall_geo(W, x, xi.w, skin, true, g);
+  wall_geo(W, x, xi.w, skin, true, t, g);
   if (!g.touching) {
     dtl[0] = dtl[1] = dtl[2] = 0.0;
     Fi[0] = Fi[1] = Fi[2] = 0.0;
@@ -772,10 +776,11 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
     return;
   }
   const double dn = g.dn < 0.0 ? 0.0 : g.dn;
-  const double arm[3] = {g.xc[0] - W.ax[0], g.xc[1] - W.ax[1], g.xc[2] - W.ax[2]};
-  const double vw[3] = {W.omega[1] * arm[2] - W.omega[2] * arm[1],
-                        W.omega[2] * arm[0] - W.omega[0] * arm[2],
-                        W.omega[0] * arm[1] - W.omega[1] * arm[0]};
+  const double ax[3] = {W.ax[0] + W.vel[0] * t, W.ax[1] + W.vel[1] * t, W.ax[2] + W.vel[2] * t};
+  const double arm[3] = {g.xc[0] - ax[0], g.xc[1] - ax[1], g.xc[2] - ax[2]};
+  const double vw[3] = {W.vel[0] + (W.omega[1] * arm[2] - W.omega[2] * arm[1]),
+                        W.vel[1] + (W.omega[2] * arm[0] - W.omega[0] * arm[2]),
+                        W.vel[2] + (W.omega[0] * arm[1] - W.omega[1] * arm[0])};
   const double Ri = xi.w;
   const double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
   const double vd[3] = {(vi.x - vw[0]) + (rw[1] * g.n[2] - rw[2] * g.n[1]),
@@ -947,7 +952,8 @@ __device__ __forceinline__ double force_particle(
                      ws.hist[(int64_t)(3 * s + 2) * n + i]};
     double Fi[3], Mi[3];
     if (t >= W.t_on && t < W.t_off) {
-      pw_contact<R>(pwi[W.material], sp.rolling, MODEL, dt, W, W.skin, xi, vi, wi, dtl, Fi, Mi);
+      pw_contact<R>(pwi[W.material], sp.rolling, MODEL, dt, W, W.skin, t, xi, vi, wi, dtl, Fi,
+                    Mi);
     } else {
       dtl[0] = dtl[1] = dtl[2] = 0.0;
       Fi[0] = Fi[1] = Fi[2] = 0.0;

@@ -91,6 +91,7 @@ SIGNATURES = {
     "dem_add_cone_wall": (C.c_int, [P, C.c_int32, DP, DP, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                     C.c_double, I32P]),
+    "dem_set_wall_motion": (C.c_int, [P, C.c_int32, C.c_int32, DP]),
     "dem_set_particles": (C.c_int, [P, C.c_int32, C.c_int64, DP, DP, DP, DP, I32P]),
     "dem_set_particles_device": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, P, P]),
     "dem_commit": (C.c_int, [P]),
@@ -227,6 +228,11 @@ class Dem:
                                                 s_min, s_max, 1 if inside else 0, material, omega,
                                                 t_on, t_off, C.byref(wid)))
         return wid.value
+
+    def set_wall_motion(self, wall_id, velocity, instance=0):
+        """Translate wall ``wall_id`` at constant ``velocity`` (before set_particles)."""
+        v = _v3(velocity)
+        self._check(self._lib.dem_set_wall_motion(self._h, instance, wall_id, _d(v)))
 
     def set_particles(self, pos, radius, vel=None, omega=None, types=None, instance=0):
         pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
@@ -370,17 +376,19 @@ class Dem:
                               m["friction"], m["rolling_friction"], instance=instance)
         for w in scene["walls"]:
             if w["kind"] == "plane":
-                self.add_planar_wall(w["point"], w["normal"], w["material"], w.get("extent"),
-                                     w.get("axis_point"), w.get("omega"), w["t_on"], w["t_off"],
-                                     instance=instance)
+                wid = self.add_planar_wall(w["point"], w["normal"], w["material"],
+                                           w.get("extent"), w.get("axis_point"), w.get("omega"),
+                                           w["t_on"], w["t_off"], instance=instance)
             elif w["kind"] == "cylinder":
-                self.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
-                                       w["s_max"], w["inside"], w["material"], w["omega"],
-                                       w["t_on"], w["t_off"], instance=instance)
+                wid = self.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"],
+                                             w["s_min"], w["s_max"], w["inside"], w["material"],
+                                             w["omega"], w["t_on"], w["t_off"], instance=instance)
             else:
-                self.add_cone_wall(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"],
-                                   w["s_min"], w["s_max"], w["inside"], w["material"],
-                                   w["omega"], w["t_on"], w["t_off"], instance=instance)
+                wid = self.add_cone_wall(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"],
+                                         w["s_min"], w["s_max"], w["inside"], w["material"],
+                                         w["omega"], w["t_on"], w["t_off"], instance=instance)
+            if w.get("velocity") is not None:
+                self.set_wall_motion(wid, w["velocity"], instance=instance)
         p = scene["particles"]
         self.set_particles(p["pos"], p["radius"], p["vel"], p["omega"], p["types"],
                            instance=instance)

@@ -55,29 +55,35 @@ def _particles(pos, radius, vel=None, omega=None, types=None):
     return dict(pos=pos, radius=radius, vel=vel, omega=omega, types=types)
 
 
+def _vel(velocity):
+    return None if velocity is None else tuple(float(v) for v in velocity)
+
+
 def plane(point, normal, material=0, extent=None, axis_point=None, omega=None,
-          t_on=-INF, t_off=INF):
+          t_on=-INF, t_off=INF, velocity=None):
+    """Plane wall; ``velocity`` translates it (None: fixed)."""
     return dict(kind="plane", point=tuple(point), normal=tuple(normal), material=material,
                 extent=None if extent is None else tuple(extent),
                 axis_point=None if axis_point is None else tuple(axis_point),
-                omega=None if omega is None else tuple(omega), t_on=t_on, t_off=t_off)
+                omega=None if omega is None else tuple(omega), t_on=t_on, t_off=t_off,
+                velocity=_vel(velocity))
 
 
 def cylinder(axis_point, axis_dir, radius, s_min, s_max, inside=True, material=0,
-             omega=0.0, t_on=-INF, t_off=INF):
+             omega=0.0, t_on=-INF, t_off=INF, velocity=None):
     return dict(kind="cylinder", axis_point=tuple(axis_point), axis_dir=tuple(axis_dir),
                 radius=float(radius), s_min=float(s_min), s_max=float(s_max),
                 inside=bool(inside), material=material, omega=float(omega), t_on=t_on,
-                t_off=t_off)
+                t_off=t_off, velocity=_vel(velocity))
 
 
 def cone(axis_point, axis_dir, radius0, slope, s_min, s_max, inside=True, material=0,
-         omega=0.0, t_on=-INF, t_off=INF):
+         omega=0.0, t_on=-INF, t_off=INF, velocity=None):
     """Cone (frustum) whose surface lies at radius0 + slope * s from the axis."""
     return dict(kind="cone", axis_point=tuple(axis_point), axis_dir=tuple(axis_dir),
                 radius0=float(radius0), slope=float(slope), s_min=float(s_min),
                 s_max=float(s_max), inside=bool(inside), material=material,
-                omega=float(omega), t_on=t_on, t_off=t_off)
+                omega=float(omega), t_on=t_on, t_off=t_off, velocity=_vel(velocity))
 
 
 def box_walls(lo, hi, material=0):
