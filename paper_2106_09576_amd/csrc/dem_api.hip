@@ -970,6 +970,7 @@ int commit(dem_ctx* c) {
     const InstDev& D = hinst[(size_t)b];
     for (WallDev w : I.walls) {
       w.skin = I.skin;
+      for (int k = 0; k < 3; ++k) w.axo[k] = w.ax[k] - w.p[k];
       hwalls.push_back(w);
     }
     for (int ta = 0; ta < kMaxTypes; ++ta)

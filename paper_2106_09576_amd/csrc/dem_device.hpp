@@ -55,6 +55,7 @@ struct WallDev {
   double skin;  // the owning instance's skin (contact-search margin)
   double slope, q;  // cone: radius + slope s at axial coordinate s; q = sqrt(1 + slope^2)
   double vel[3];
+  double axo[3];  // ax - p: the rotation axis moves with the wall
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).

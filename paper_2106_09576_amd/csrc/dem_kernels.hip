@@ -257,10 +257,11 @@ hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint3
 
 // Candidate / touching predicates of particle centre x (radius R) against a
 // wall at time t, evaluated without square roots; when touching also the unit
-// normal from the particle to the wall, the overlap and the contact point.
+// normal from the particle to the wall, the overlap and the lever arm of the
+// contact point about the wall's rotation axis (x_c - ax(t)).
 struct WallGeo {
   bool candidate, touching;
-  double n[3], dn, xc[3];
+  double n[3], dn, arm[3];
 };
 
 __device__ inline double dot3(const double* a, const double* b) {
@@ -284,7 +285,7 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
     if (g.touching && need_contact) {
       for (int k = 0; k < 3; ++k) {
         g.n[k] = -W.nrm[k];
-        g.xc[k] = x[k] - dist * W.nrm[k];
+        g.arm[k] = (rel[k] - dist * W.nrm[k]) - W.axo[k];
       }
       g.dn = R - dist;
     }
@@ -323,7 +324,7 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
       for (int k = 0; k < 3; ++k) {
         const double m = (er[k] - W.slope * W.nrm[k]) / q;
         g.n[k] = W.inside ? m : -m;
-        g.xc[k] = x[k] + dist * g.n[k];
+        g.arm[k] = (rel[k] + dist * g.n[k]) - W.axo[k];
       }
     }
     return;
@@ -351,7 +352,7 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
     g.dn = R - dist;
     for (int k = 0; k < 3; ++k) {
       g.n[k] = W.inside ? er[k] : -er[k];
-      g.xc[k] = P[k] + sax * W.nrm[k] + Rc * er[k];
+      g.arm[k] = (sax * W.nrm[k] + Rc * er[k]) - W.axo[k];
     }
   }
 }
@@ -776,8 +777,7 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
     return;
   }
   const double dn = g.dn < 0.0 ? 0.0 : g.dn;
-  const double ax[3] = {W.ax[0] + W.vel[0] * t, W.ax[1] + W.vel[1] * t, W.ax[2] + W.vel[2] * t};
-  const double arm[3] = {g.xc[0] - ax[0], g.xc[1] - ax[1], g.xc[2] - ax[2]};
+  const double* arm = g.arm;
   const double vw[3] = {W.vel[0] + (W.omega[1] * arm[2] - W.omega[2] * arm[1]),
                         W.vel[1] + (W.omega[2] * arm[0] - W.omega[0] * arm[2]),
                         W.vel[2] + (W.omega[0] * arm[1] - W.omega[1] * arm[0])};
@@ -1032,8 +1032,10 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v,
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
 }
 
+// Occupancy floor: the nonlinear law fits 128 VGPRs (four wavefronts per
+// SIMD) without spills; the linear law needs more and keeps three.
 template <typename R, int MODE, int MODEL, int BS>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(MODEL == 0 ? 4 : 3)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
         const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
         ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
