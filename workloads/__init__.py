@@ -409,3 +409,76 @@ def batched_drums(n_inst=256, n_min=2000, n_max=50000, d=3.0e-3, seed=4, dt=5.0e
         sc["name"] = f"drum{k}_{n}"
         scenes.append(sc)
     return scenes
+
+
+# Material of the parameter file printed in the paper's appendix (particles
+# and walls alike): d = 5 mm, rho 2000, E 1 MPa, nu 0.3, e 0.3, mu 0.1,
+# mu_r 0.05.
+APPENDIX_MATERIAL = dict(density=2000.0, youngs=1.0e6, poisson=0.3, restitution=0.3,
+                         friction=0.1, rolling_friction=0.05)
+
+
+def sliding_floor_scene(n=20, d=5.0e-3, half=0.07, floor_speed=0.15, seed=19, dt=1.0e-5,
+                        K=20):
+    """The case of the appendix parameter file: a cube [-0.07, 0.07]^3 whose
+    floor (boundary z = -0.07) translates at 0.15 m/s along x, 20 spheres of
+    5 mm dropped from the insertion box [-0.05, 0.05]^2 x [-0.06, 0] (placed
+    at seeded random non-overlapping positions, at rest, instead of being
+    inserted during the run), dt 1e-5 s, a search every 20 steps, threshold
+    1.3, constant rolling resistance, velocity Verlet, gravity -z."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = d / 2
+    pos = rsa_box(n, R, (-0.05 + R, -0.05 + R, -0.06 + R), (0.05 - R, 0.05 - R, 0.0 - R), rng)
+    lo, hi = (-half,) * 3, (half,) * 3
+    walls = box_walls(lo, hi)
+    walls[4] = dict(walls[4], velocity=(float(floor_speed), 0.0, 0.0))  # the floor
+    m = 2 * d
+    return dict(name=f"sliding_floor_{n}",
+                config=_cfg(dt, tuple(v - m for v in lo), tuple(v + m for v in hi), K=K),
+                materials=[dict(APPENDIX_MATERIAL)], walls=walls, particles=_particles(pos, R))
+
+
+def dam_break_scene(n=1_280_000, d=1.0e-3, length=0.4, height=0.2, t_dam=0.5, seed=5,
+                    dt=1.0e-5, K=20, spacing=1.02, jitter=0.01, threshold=1.3,
+                    material=None, depth=None):
+    """Dam break (the paper's weak-scaling scene): spheres at rest in the left
+    half of a box of length 0.4 m (x) and height 0.2 m (y, gravity -y), held
+    by a floating dam (a plane at x = length / 2) that is removed at t_dam;
+    then they spread over the whole length.  The depth (z) grows with n at
+    the table's ratio of 0.01 m per 160,000 spheres unless given (small test
+    cases).  Spheres of 1 mm on a jittered lattice (spacing 1.02 d, jitter
+    +-0.01 d, its first column 1.02 radii from the dam) filling the left half
+    from the bottom; the appendix material."""
+    mat = dict(APPENDIX_MATERIAL if material is None else material)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = d / 2
+    depth = 0.01 * n / 160_000 if depth is None else float(depth)
+    a = spacing * d
+    c = 1.02 * r
+    # enough layers for n spheres (at least one row of cells across the depth)
+    per_layer = max(1, int((length / 2 - 2 * c) / a + 1)) * max(1, int((depth - 2 * c) / a + 1))
+    layers = n / per_layer + 2
+    while True:
+        top = min(height - c, c + a * layers)
+        g = jittered_lattice((c, c, c), (length / 2 - c, top, depth - c), a, jitter * d, rng)
+        keep = ((g[:, 0] >= c) & (g[:, 0] <= length / 2 - c) & (g[:, 1] >= c) &
+                (g[:, 2] >= c) & (g[:, 2] <= depth - c))
+        g = g[keep]
+        if g.shape[0] >= n:
+            break
+        if top >= height - c:
+            raise RuntimeError(f"dam break: only {g.shape[0]} lattice sites for {n} spheres")
+        layers += 2
+    g[:, 0] = length / 2 - g[:, 0]  # columns counted from the dam
+    g = g[np.lexsort((g[:, 2], g[:, 0], g[:, 1]))[:n]]  # lowest y first
+    g = g[rng.permutation(n)]
+    lo, hi = (0.0, 0.0, 0.0), (length, height, depth)
+    walls = [plane((0.0, 0.0, 0.0), (1.0, 0.0, 0.0)), plane((length, 0.0, 0.0), (-1.0, 0.0, 0.0)),
+             plane((0.0, 0.0, 0.0), (0.0, 1.0, 0.0)),
+             plane((0.0, 0.0, 0.0), (0.0, 0.0, 1.0)), plane((0.0, 0.0, depth), (0.0, 0.0, -1.0)),
+             plane((length / 2, 0.0, 0.0), (-1.0, 0.0, 0.0), t_off=float(t_dam))]
+    m = 2 * d
+    cfg = _cfg(dt, (-m, -m, -m), (length + m, height + m, depth + m), threshold=threshold, K=K,
+               gravity=(0.0, -9.81, 0.0))
+    return dict(name=f"dam_break_{n}", config=cfg, materials=[mat], walls=walls,
+                particles=_particles(g, r), geometry=dict(length=length, depth=depth))
