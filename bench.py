@@ -13,8 +13,8 @@ One step = contact search when due (the "dynamic" schedule: when a particle
 may have moved half the skin) + particle-particle and particle-wall
 Hertz-Mindlin forces with tangential history + velocity-Verlet integration,
 all in the library's HIP kernels.  Also timed: the same drum with a search
-every 20 steps, with live autotuning, and the batch of 256 drums.  Prints
-one JSON line.
+every 20 steps, with live autotuning, the batch of 256 drums, the dam break
+of 1.28M spheres and the 1,000-sphere box.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -65,22 +65,25 @@ def load_traffic(precision):
     return None if e is None else float(e)
 
 
-def measure(args, precision, scene, label=None, autotune=False, force_block=0):
+def measure(args, precision, scene, label=None, autotune=False, force_block=0, warmup=None,
+            steps=None):
     import torch
     from paper_2106_09576_amd import Dem
 
+    warmup = args.warmup if warmup is None else warmup
+    n_steps = args.steps if steps is None else steps
     precision_name = precision
     precision = label or precision
     log(f"{precision}: uploading {scene['particles']['pos'].shape[0]} particles")
     sim = Dem.from_scene(scene, precision=precision_name, force_block=force_block)
     stream = torch.cuda.ExternalStream(sim.stream())
-    log(f"{precision}: warmup {args.warmup} steps (drum settles, contacts form)")
+    log(f"{precision}: warmup {warmup} steps (the bed settles, contacts form)")
     done = 0
-    while done < args.warmup:
-        k = min(args.warmup - done, 5000)
+    while done < warmup:
+        k = min(warmup - done, 5000)
         sim.step(k)
         done += k
-        log(f"{precision}: warmup {done}/{args.warmup}")
+        log(f"{precision}: warmup {done}/{warmup}")
     tune = None
     if autotune:
         tune = sim.autotune(trial_steps=args.tune_steps)
@@ -92,10 +95,10 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    log(f"{precision}: timing {args.steps} steps")
+    log(f"{precision}: timing {n_steps} steps")
     t0 = time.perf_counter()
     ev0.record(stream)
-    sim.step(args.steps)
+    sim.step(n_steps)
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -106,7 +109,7 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0):
     pairs = 0.25 * (st0["n_list_entries"] + st1["n_list_entries"])
     touching = 0.25 * (st0["n_touching"] + st1["n_touching"])
     # per-kernel durations with HIP events (eager launches, same kernels)
-    n_t = min(args.steps, 200)
+    n_t = min(n_steps, 200)
     sim.set_timing(True)
     sim.step(n_t)
     tm = sim.get_timing()
@@ -117,13 +120,13 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0):
     achieved = algo_bytes / (force_ms * 1e-3) / 1e9
     res = dict(
         precision=precision_name,
-        value=n_active * args.steps / wall,
-        ms_per_step=1e3 * wall / args.steps,
-        event_ms_per_step=ev_ms / args.steps,
+        value=n_active * n_steps / wall,
+        ms_per_step=1e3 * wall / n_steps,
+        event_ms_per_step=ev_ms / n_steps,
         n_active=int(n_active),
         pairs_per_particle=pairs / max(n_active, 1),
         touching_per_particle=touching / max(n_active, 1),
-        contacts_per_s=touching * args.steps / wall,
+        contacts_per_s=touching * n_steps / wall,
         force_kernel_ms=force_ms,
         search_ms=search_ms,
         force_kernel_algo_bytes=algo_bytes,
@@ -225,6 +228,25 @@ def measure_small_box(args):
             "results": res, "fp32_law_vs_fp64": err}
 
 
+def measure_dam_break(args, precs):
+    """The dam break of the weak-scaling study at one GPU's share: 1.28M
+    spheres of 1 mm (the table's 20k per core on 64 cores, box depth
+    0.08 m) held by the dam for the first steps, which then flow; timed
+    right after the dam's removal, while the front collapses (particles in
+    motion, frequent searches)."""
+    import workloads as W
+    dt = 1e-5
+    sc = W.dam_break_scene(n=args.dam_n, t_dam=args.dam_steps * dt, dt=dt)
+    sc = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+    res = {p: measure(args, p, sc, label=f"{p} dam break", force_block=MAIN_FORCE_BLOCK,
+                      warmup=args.dam_steps, steps=args.dam_steps) for p in precs}
+    return {"workload": (f"dam break, {args.dam_n} spheres d=1mm in a 0.4 m x 0.2 m box of "
+                         f"depth {sc['geometry']['depth']:.3f} m, appendix material, dt=1e-5 s, "
+                         f"r_s=1.3 d, dynamic search; the dam is removed after "
+                         f"{args.dam_steps} steps and the next {args.dam_steps} are timed"),
+            "results": res}
+
+
 def copy_bandwidth():
     """Achievable device bandwidth: five copies of 1 GiB (read 1 GiB, write
     1 GiB each) timed with HIP events, after one untimed copy."""
@@ -284,6 +306,10 @@ def main():
                     help="skip the autotuned legs (drum) and autotuning of the batch")
     ap.add_argument("--tune-steps", type=int, default=200,
                     help="steps per autotuner trial")
+    ap.add_argument("--skip-dam", action="store_true", help="skip the dam-break legs")
+    ap.add_argument("--dam-n", type=int, default=1_280_000)
+    ap.add_argument("--dam-steps", type=int, default=4000,
+                    help="steps with the dam standing, then timed steps after its removal")
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--batch-warmup", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -389,6 +415,8 @@ def main():
         }
         if "fp32" in b and "fp64" in b:
             out["batched"]["fp32_vs_fp64"] = b["fp32"]["value"] / b["fp64"]["value"]
+    if not args.skip_dam:
+        out["dam_break"] = measure_dam_break(args, precs)
     if not args.skip_small:
         out["small_box"] = measure_small_box(args)
     if not args.skip_cpu:
