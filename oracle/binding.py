@@ -73,6 +73,12 @@ def _load():
         lib.ora_add_cone.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
                                      C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
                                      C.POINTER(C.c_int32)]
+        lib.ora_add_mesh.argtypes = [P, C.c_int64, D, C.c_int64, C.POINTER(C.c_int32),
+                                     C.c_int32, D, D, C.c_double, C.c_double,
+                                     C.POINTER(C.c_int32)]
+        lib.ora_get_mesh_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                              C.POINTER(C.c_int64)]
+        lib.ora_triangle_closest.argtypes = [D, D, D]
         lib.ora_step.argtypes = [P, C.c_int64]
         lib.ora_set_wall_velocity.argtypes = [P, C.c_int32, D]
         lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
@@ -186,6 +192,30 @@ class OracleSim:
                                       C.byref(wid)), "ora_add_cone")
         return wid.value
 
+    def add_mesh(self, vertices, triangles, material=0, axis_point=None, omega=None,
+                 t_on=-np.inf, t_off=np.inf):
+        V = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+        T = np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3)
+        wid = C.c_int32()
+        ap, om = _vec(axis_point), _vec(omega)
+        _check(self._lib.ora_add_mesh(self._h, V.shape[0], _dp(V), T.shape[0],
+                                      T.ctypes.data_as(C.POINTER(C.c_int32)), material,
+                                      _dp(ap), _dp(om), t_on, t_off, C.byref(wid)),
+               "ora_add_mesh")
+        return wid.value
+
+    def mesh_contacts(self):
+        """(particle, wall, triangle) candidate triples and their overlaps."""
+        cnt = C.c_int64()
+        self._lib.ora_get_mesh_contacts(self._h, 0, None, None, C.byref(cnt))
+        m = cnt.value
+        tr = np.empty((max(m, 1), 3), dtype=np.int64)
+        dt = np.empty((max(m, 1), 3))
+        _check(self._lib.ora_get_mesh_contacts(self._h, max(m, 1),
+                                               tr.ctypes.data_as(C.POINTER(C.c_int64)),
+                                               _dp(dt), C.byref(cnt)), "ora_get_mesh_contacts")
+        return tr[:m], dt[:m]
+
     def set_wall_velocity(self, wall_id, vel):
         v = _vec(vel)
         _check(self._lib.ora_set_wall_velocity(self._h, wall_id, _dp(v)), "ora_set_wall_velocity")
@@ -281,6 +311,20 @@ class OracleSim:
         return {"F": F, "Mi": Mi, "Mj": Mj, "delta_t": dt, "touching": bool(touch.value)}
 
 
+def triangle_closest(corners, x):
+    """The oracle's closest point of a triangle to x: (feature, signed plane
+    distance, squared distance, point); feature 'face', ('edge', a) for the
+    edge from corner a to a + 1, ('vertex', a)."""
+    lib = _load()
+    c = np.ascontiguousarray(corners, dtype=np.float64).reshape(9)
+    xx = _vec(x)
+    out = np.empty(6)
+    _check(lib.ora_triangle_closest(_dp(c), _dp(xx), _dp(out)), "ora_triangle_closest")
+    f = int(out[0])
+    feat = "face" if f == 0 else (("edge", f - 1) if f < 4 else ("vertex", f - 4))
+    return feat, out[1], out[2], out[3:6].copy()
+
+
 def oracle_from_scene(scene: dict) -> OracleSim:
     """Build an oracle simulation from a scene dictionary (see ``workloads``)."""
     c = scene["config"]
@@ -301,6 +345,9 @@ def oracle_from_scene(scene: dict) -> OracleSim:
             sim.add_cylinder(w["axis_point"], w["axis_dir"], w["radius"], w["s_min"],
                              w["s_max"], w["inside"], w["material"], w["omega"], w["t_on"],
                              w["t_off"])
+        elif w["kind"] == "mesh":
+            sim.add_mesh(w["vertices"], w["triangles"], w["material"], w.get("axis_point"),
+                         w.get("omega"), w["t_on"], w["t_off"])
         else:
             sim.add_cone(w["axis_point"], w["axis_dir"], w["radius0"], w["slope"], w["s_min"],
                          w["s_max"], w["inside"], w["material"], w["omega"], w["t_on"],

@@ -28,9 +28,9 @@
  *             cells listed without repetition, then a fine search that keeps
  *             pairs closer than a threshold; Sec. 3.1: searched every n steps
  *   Sec. 3.7                       moving (rotating and translating) and floating
- *                                  walls
- *   walls are analytic surfaces (plane, cylinder, cone) standing in for the
- *   paper's meshed boundaries
+ *                                  walls; particle-face, particle-line and
+ *                                  particle-point contacts with meshed walls
+ *   walls are analytic surfaces (plane, cylinder, cone) or triangle meshes
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
  *   - the undefined force F^c in the tangential torque is the tangential force;
@@ -68,7 +68,7 @@
 #define PI 3.14159265358979323846
 
 typedef struct {
-  int kind; /* 0 plane, 1 cylinder, 2 cone */
+  int kind; /* 0 plane, 1 cylinder, 2 cone, 3 triangle mesh */
   double p[3];     /* plane point / axis point */
   double nrm[3];   /* plane normal (into the domain) / axis direction */
   int bounded;
@@ -81,7 +81,16 @@ typedef struct {
   double ax[3];    /* a point on the rotation axis */
   double t_on, t_off;
   double vel[3];   /* translational velocity: p and ax move with it */
+  int64_t tri_begin, ntri; /* mesh: its triangles in the simulation's list */
 } ora_wall;
+
+/* One triangle of a mesh wall: corners at time 0 (the front side, where the
+   particles are, is the side of (p1 - p0) x (p2 - p0)) and the mesh's own
+   indices of the corners, which name its edges and vertices. */
+typedef struct {
+  double p[3][3];
+  int32_t v[3];
+} ora_tri;
 
 /* The wall at time t: its point and rotation axis translated by vel t. */
 static ora_wall wall_at(const ora_wall* W, double t) {
@@ -104,6 +113,14 @@ typedef struct {
   double dt[3];
 } ora_wpair;
 
+/* particle-triangle candidate of a mesh wall */
+typedef struct {
+  int64_t i;
+  int32_t w;
+  int64_t tri; /* index in the simulation's triangle list */
+  double dt[3];
+} ora_mpair;
+
 struct ora_sim {
   ora_config cfg;
   ora_material mat[ORA_MAX_TYPES];
@@ -120,6 +137,10 @@ struct ora_sim {
   int64_t npairs;
   ora_wpair* wpairs;
   int64_t nwpairs;
+  ora_tri* tris;
+  int64_t ntris;
+  ora_mpair* mpairs;
+  int64_t nmpairs;
   int64_t step;
   int ready;
 };
@@ -432,21 +453,17 @@ static void wall_geometry(const ora_wall* W, const double* x, double R, double s
 
 static int wall_enabled(const ora_wall* W, double t) { return t >= W->t_on && t < W->t_off; }
 
-/* Particle-wall contact, same law with the wall as body j. */
-static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const double* x,
-                      const double* v, const double* w, double R, double m, int ti,
-                      double* delta_t, double* Fi, double* Mi, double* fmag) {
-  for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = 0.0;
-  *fmag = 0.0;
-  const ora_wall Wt = wall_at(W, t);
-  W = &Wt;
+/* The contact law against a wall (W at the current time) touching with unit
+   normal n (from the particle to the wall), overlap dn and contact point xc. */
+static void wall_law(const ora_sim* s, const ora_wall* W, const double* v, const double* w,
+                     double R, double m, int ti, const double* n, double dn_geo,
+                     const double* xc, double* delta_t, double* Fi, double* Mi, double* fmag) {
   ora_wgeo g;
-  wall_geometry(W, x, R, s->skin, &g);
-  if (!wall_enabled(W, t) || !g.touching) {
-    delta_t[0] = delta_t[1] = delta_t[2] = 0.0;
-    return 0;
+  for (int k = 0; k < 3; ++k) {
+    g.n[k] = n[k];
+    g.xc[k] = xc[k];
   }
-  double dn = g.dn < 0.0 ? 0.0 : g.dn;
+  double dn = dn_geo < 0.0 ? 0.0 : dn_geo;
   /* velocity of the wall surface at the contact point:
      v_wall + Omega x (x_c - axis point) */
   double arm[3], vw[3];
@@ -478,7 +495,206 @@ static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const doubl
   vcross(rrel, g.n, vroll);
   double Mj[3];
   contact_law(&cp, &s->cfg, dn, g.n, vij, wrel, vroll, R, 0.0, delta_t, Fi, Mi, Mj, fmag);
+}
+
+/* Particle-wall contact, same law with the wall as body j. */
+static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const double* x,
+                      const double* v, const double* w, double R, double m, int ti,
+                      double* delta_t, double* Fi, double* Mi, double* fmag) {
+  for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = 0.0;
+  *fmag = 0.0;
+  const ora_wall Wt = wall_at(W, t);
+  W = &Wt;
+  ora_wgeo g;
+  wall_geometry(W, x, R, s->skin, &g);
+  if (!wall_enabled(W, t) || !g.touching) {
+    delta_t[0] = delta_t[1] = delta_t[2] = 0.0;
+    return 0;
+  }
+  wall_law(s, W, v, w, R, m, ti, g.n, g.dn, g.xc, delta_t, Fi, Mi, fmag);
   return 1;
+}
+
+/* ----------------------------------------------------------- mesh walls
+
+   A mesh wall is a rigid surface of triangles (Sec. 3.7: particles collide
+   with boundary faces, lines and points).  The closest point of a closed
+   triangle to a particle centre x is the projection of x onto the
+   triangle's plane when that projection lies strictly inside all three
+   edges (a face contact), else the closest of the three edges' closest
+   points (the projection onto the edge line clamped to the edge), which is
+   an edge when the projection falls strictly inside the edge and a corner
+   otherwise (line and point contacts). */
+typedef struct {
+  int feature;  /* 0 face, 1 edge, 2 vertex */
+  int a, b;     /* edge: its corners a, a + 1 (mod 3); vertex: corner a */
+  double s;     /* signed distance of x from the plane, along the unit normal */
+  double d2;    /* squared distance from x to the closest point */
+  double q[3];  /* the closest point */
+  double n[3];  /* unit normal of the triangle (front side) */
+} ora_trigeo;
+
+/* T's corners move with the wall: at time t they are at p + vel t; the
+   normal and the edge vectors are those of the corners at time 0. */
+static void triangle_closest(const ora_tri* T, const double* vel, double t, const double* x,
+                             ora_trigeo* g) {
+  double P[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int k = 0; k < 3; ++k) P[c][k] = T->p[c][k] + vel[k] * t;
+  double e01[3], e02[3], N[3];
+  vsub(T->p[1], T->p[0], e01);
+  vsub(T->p[2], T->p[0], e02);
+  vcross(e01, e02, N);
+  const double len = vnorm(N);
+  for (int k = 0; k < 3; ++k) g->n[k] = N[k] / len;
+  double rel[3];
+  vsub(x, P[0], rel);
+  g->s = vdot(rel, g->n);
+  /* inside: x lies on the inner side of every edge, strictly */
+  int inside = 1;
+  for (int c = 0; c < 3; ++c) {
+    double E[3], r[3], cr[3];
+    vsub(T->p[(c + 1) % 3], T->p[c], E);
+    vsub(x, P[c], r);
+    vcross(E, r, cr);
+    if (!(vdot(cr, g->n) > 0.0)) inside = 0;
+  }
+  if (inside) {
+    g->feature = 0;
+    g->a = g->b = 0;
+    for (int k = 0; k < 3; ++k) g->q[k] = x[k] - g->s * g->n[k];
+    g->d2 = g->s * g->s;
+    return;
+  }
+  g->d2 = INFINITY;
+  for (int c = 0; c < 3; ++c) {
+    double E[3], r[3], q[3], dq[3];
+    vsub(T->p[(c + 1) % 3], T->p[c], E);
+    vsub(x, P[c], r);
+    const double u = vdot(r, E) / vdot(E, E);
+    const double uc = u <= 0.0 ? 0.0 : (u >= 1.0 ? 1.0 : u);
+    for (int k = 0; k < 3; ++k) q[k] = P[c][k] + uc * E[k];
+    vsub(x, q, dq);
+    const double d2 = vdot(dq, dq);
+    if (d2 < g->d2) {
+      g->d2 = d2;
+      for (int k = 0; k < 3; ++k) g->q[k] = q[k];
+      if (u <= 0.0) {
+        g->feature = 2;
+        g->a = g->b = c;
+      } else if (u >= 1.0) {
+        g->feature = 2;
+        g->a = g->b = (c + 1) % 3;
+      } else {
+        g->feature = 1;
+        g->a = c;
+        g->b = (c + 1) % 3;
+      }
+    }
+  }
+}
+
+/* A triangle is a candidate of a particle when the centre is less than R
+   behind its plane and closer than R + skin to the closed triangle. */
+static int triangle_candidate(const ora_trigeo* g, double R, double skin) {
+  const double m = R + skin;
+  return g->s > -R && g->d2 < m * m;
+}
+
+/* Identity of a triangle's closest feature within its mesh: faces by
+   triangle, edges by their two corner indices (smaller first), vertices by
+   corner index. */
+typedef struct {
+  int kind;
+  int64_t a, b;
+} ora_feature;
+
+static ora_feature feature_of(const ora_tri* T, int64_t tri, const ora_trigeo* g) {
+  ora_feature f;
+  f.kind = g->feature;
+  if (g->feature == 0) {
+    f.a = tri;
+    f.b = -1;
+  } else if (g->feature == 1) {
+    const int64_t va = T->v[g->a], vb = T->v[g->b];
+    f.a = va < vb ? va : vb;
+    f.b = va < vb ? vb : va;
+  } else {
+    f.a = T->v[g->a];
+    f.b = -1;
+  }
+  return f;
+}
+
+static int tri_has_vertex(const ora_tri* T, int64_t v) {
+  return T->v[0] == v || T->v[1] == v || T->v[2] == v;
+}
+
+/* Contacts of particle i with one mesh wall, from its candidate triangles
+   M[0..m) (ascending): the points of the surface where the distance from
+   the centre has a local minimum closer than R.  Every candidate reports
+   its closest point and the feature it lies on.  A face is in contact when
+   the centre is less than R above its plane.  The distance restricted to
+   one triangle is convex, so a point on an edge or a vertex is a local
+   minimum of the surface exactly when every triangle around it has it as
+   its own closest point: an edge or vertex counts when every candidate
+   triangle that contains it reports it, once, evaluated by the first
+   candidate that reports it, whose slot keeps the tangential overlap.  All
+   other slots start over from zero. */
+static void mesh_contacts(ora_sim* s, const ora_wall* W0, double t, ora_mpair* M, int64_t m) {
+  const int64_t i = M[0].i;
+  const double* x = &s->x[3 * i];
+  const double R = s->R[i];
+  const ora_wall Wt = wall_at(W0, t);
+  const int on = wall_enabled(&Wt, t);
+  ora_trigeo* G = (ora_trigeo*)malloc(sizeof(ora_trigeo) * (size_t)m);
+  ora_feature* Fe = (ora_feature*)malloc(sizeof(ora_feature) * (size_t)m);
+  for (int64_t k = 0; k < m; ++k) {
+    triangle_closest(&s->tris[M[k].tri], W0->vel, t, x, &G[k]);
+    Fe[k] = feature_of(&s->tris[M[k].tri], M[k].tri, &G[k]);
+  }
+  for (int64_t k = 0; k < m; ++k) {
+    int contact = 0;
+    if (on) {
+      if (Fe[k].kind == 0) {
+        contact = G[k].s < R;
+      } else {
+        int dropped = 0, owner = 1;
+        for (int64_t j = 0; j < m && !dropped; ++j) {
+          const ora_tri* Tj = &s->tris[M[j].tri];
+          const int same = Fe[j].kind == Fe[k].kind && Fe[j].a == Fe[k].a && Fe[j].b == Fe[k].b;
+          const int contains = tri_has_vertex(Tj, Fe[k].a) &&
+                               (Fe[k].kind == 2 || tri_has_vertex(Tj, Fe[k].b));
+          if (contains && !same) dropped = 1;
+          if (j < k && same) owner = 0;
+        }
+        contact = !dropped && owner && G[k].d2 < R * R && G[k].d2 > 0.0;
+      }
+    }
+    if (!contact) {
+      M[k].dt[0] = M[k].dt[1] = M[k].dt[2] = 0.0;
+      continue;
+    }
+    double n[3], dn;
+    if (Fe[k].kind == 0) {
+      for (int c = 0; c < 3; ++c) n[c] = -G[k].n[c];
+      dn = R - G[k].s;
+    } else {
+      const double dist = sqrt(G[k].d2);
+      for (int c = 0; c < 3; ++c) n[c] = (G[k].q[c] - x[c]) / dist;
+      dn = R - dist;
+    }
+    double Fi[3], Mi[3], fm;
+    wall_law(s, &Wt, &s->v[3 * i], &s->w[3 * i], R, s->m[i], s->type[i], n, dn, G[k].q,
+             M[k].dt, Fi, Mi, &fm);
+    for (int c = 0; c < 3; ++c) {
+      s->F[3 * i + c] += Fi[c];
+      s->T[3 * i + c] += Mi[c];
+    }
+    s->S[i] += fm;
+  }
+  free(G);
+  free(Fe);
 }
 
 /* ------------------------------------------------------------------ search */
@@ -660,6 +876,7 @@ static int rebuild(ora_sim* s) {
   for (int64_t i = 0; i < s->n; ++i) {
     if (!s->active[i]) continue;
     for (int w = 0; w < s->nw; ++w) {
+      if (s->walls[w].kind == 3) continue;
       ora_wgeo g;
       const ora_wall Wt = wall_at(&s->walls[w], t_search);
       wall_geometry(&Wt, &s->x[3 * i], s->R[i], s->skin, &g);
@@ -687,6 +904,47 @@ static int rebuild(ora_sim* s) {
   free(s->wpairs);
   s->wpairs = W;
   s->nwpairs = cnt;
+
+  /* particle-triangle candidates of mesh walls, in (gid, wall, triangle)
+     order, every triangle of the mesh tested */
+  int64_t mcap = 64, mcnt = 0, mold = 0;
+  ora_mpair* Mp = (ora_mpair*)malloc(sizeof(ora_mpair) * (size_t)mcap);
+  if (!Mp) return ORA_ENOMEM;
+  for (int64_t i = 0; i < s->n; ++i) {
+    if (!s->active[i]) continue;
+    for (int w = 0; w < s->nw; ++w) {
+      const ora_wall* Wm = &s->walls[w];
+      if (Wm->kind != 3) continue;
+      for (int64_t tr = Wm->tri_begin; tr < Wm->tri_begin + Wm->ntri; ++tr) {
+        ora_trigeo g;
+        triangle_closest(&s->tris[tr], Wm->vel, t_search, &s->x[3 * i], &g);
+        if (!triangle_candidate(&g, s->R[i], s->skin)) continue;
+        if (mcnt == mcap) {
+          mcap *= 2;
+          ora_mpair* Q = (ora_mpair*)realloc(Mp, sizeof(ora_mpair) * (size_t)mcap);
+          if (!Q) {
+            free(Mp);
+            return ORA_ENOMEM;
+          }
+          Mp = Q;
+        }
+        Mp[mcnt].i = i;
+        Mp[mcnt].w = w;
+        Mp[mcnt].tri = tr;
+        Mp[mcnt].dt[0] = Mp[mcnt].dt[1] = Mp[mcnt].dt[2] = 0.0;
+        /* triangles are numbered in wall order, so (i, tri) orders the list */
+        while (mold < s->nmpairs && (s->mpairs[mold].i < i ||
+                                     (s->mpairs[mold].i == i && s->mpairs[mold].tri < tr)))
+          ++mold;
+        if (mold < s->nmpairs && s->mpairs[mold].i == i && s->mpairs[mold].tri == tr)
+          memcpy(Mp[mcnt].dt, s->mpairs[mold].dt, sizeof(double) * 3);
+        ++mcnt;
+      }
+    }
+  }
+  free(s->mpairs);
+  s->mpairs = Mp;
+  s->nmpairs = mcnt;
   return ORA_OK;
 }
 
@@ -722,6 +980,15 @@ static void compute_forces(ora_sim* s, double t) {
       s->T[3 * i + k] += Mi[k];
     }
     s->S[i] += fm;
+  }
+  /* mesh walls: the candidates of one particle and one mesh together */
+  for (int64_t p = 0; p < s->nmpairs;) {
+    int64_t q = p + 1;
+    while (q < s->nmpairs && s->mpairs[q].i == s->mpairs[p].i &&
+           s->mpairs[q].w == s->mpairs[p].w)
+      ++q;
+    mesh_contacts(s, &s->walls[s->mpairs[p].w], t, &s->mpairs[p], q - p);
+    p = q;
   }
 }
 
@@ -804,15 +1071,16 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
 static void free_particles(ora_sim* s) {
   free(s->x); free(s->v); free(s->w); free(s->R); free(s->m); free(s->I);
   free(s->F); free(s->T); free(s->S); free(s->xref); free(s->type); free(s->active);
-  free(s->pairs); free(s->wpairs);
+  free(s->pairs); free(s->wpairs); free(s->mpairs);
   s->x = s->v = s->w = s->R = s->m = s->I = s->F = s->T = s->S = s->xref = NULL;
-  s->type = NULL; s->active = NULL; s->pairs = NULL; s->wpairs = NULL;
-  s->npairs = s->nwpairs = 0;
+  s->type = NULL; s->active = NULL; s->pairs = NULL; s->wpairs = NULL; s->mpairs = NULL;
+  s->npairs = s->nwpairs = s->nmpairs = 0;
 }
 
 void ora_destroy(ora_sim* s) {
   if (!s) return;
   free_particles(s);
+  free(s->tris);
   free(s);
 }
 
@@ -1003,6 +1271,71 @@ int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3
   return ORA_OK;
 }
 
+int ora_add_mesh(ora_sim* s, int64_t n_vertices, const double* vertices, int64_t n_triangles,
+                 const int32_t* triangles, int32_t material, const double axis_point[3],
+                 const double omega[3], double t_on, double t_off, int32_t* wall_id) {
+  if (!s || !vertices || !triangles || s->nw >= ORA_MAX_WALLS) return ORA_EINVAL;
+  if (n_vertices < 3 || n_triangles < 1 || n_vertices > ((int64_t)1 << 30)) return ORA_EINVAL;
+  if (material < 0 || material >= ORA_MAX_TYPES || !s->mat_set[material]) return ORA_EINVAL;
+  if (s->n > 0) return ORA_ESTATE;
+  for (int64_t k = 0; k < 3 * n_vertices; ++k)
+    if (!isfinite(vertices[k])) return ORA_EINVAL;
+  ora_tri* T = (ora_tri*)realloc(s->tris, sizeof(ora_tri) * (size_t)(s->ntris + n_triangles));
+  if (!T) return ORA_ENOMEM;
+  s->tris = T;
+  for (int64_t f = 0; f < n_triangles; ++f) {
+    ora_tri* t = &s->tris[s->ntris + f];
+    for (int c = 0; c < 3; ++c) {
+      const int32_t v = triangles[3 * f + c];
+      if (v < 0 || v >= n_vertices) return ORA_EINVAL;
+      t->v[c] = v;
+      for (int k = 0; k < 3; ++k) t->p[c][k] = vertices[3 * (int64_t)v + k];
+    }
+    /* no degenerate triangles: the normal must exist */
+    double e01[3], e02[3], N[3];
+    vsub(t->p[1], t->p[0], e01);
+    vsub(t->p[2], t->p[0], e02);
+    vcross(e01, e02, N);
+    const double len = vnorm(N);
+    if (!(len > 0.0) || !isfinite(len)) return ORA_EINVAL;
+  }
+  ora_wall W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 3;
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = vertices[k];
+    W.ax[k] = axis_point ? axis_point[k] : vertices[k];
+    W.omega[k] = omega ? omega[k] : 0.0;
+  }
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  W.tri_begin = s->ntris;
+  W.ntri = n_triangles;
+  s->ntris += n_triangles;
+  s->walls[s->nw] = W;
+  if (wall_id) *wall_id = s->nw;
+  s->nw += 1;
+  return ORA_OK;
+}
+
+int ora_triangle_closest(const double corners[9], const double x[3], double out[6]) {
+  if (!corners || !x || !out) return ORA_EINVAL;
+  ora_tri T;
+  for (int c = 0; c < 3; ++c) {
+    T.v[c] = c;
+    for (int k = 0; k < 3; ++k) T.p[c][k] = corners[3 * c + k];
+  }
+  const double zero[3] = {0.0, 0.0, 0.0};
+  ora_trigeo g;
+  triangle_closest(&T, zero, 0.0, x, &g);
+  out[0] = g.feature == 0 ? 0.0 : (g.feature == 1 ? 1.0 + g.a : 4.0 + g.a);
+  out[1] = g.s;
+  out[2] = g.d2;
+  for (int k = 0; k < 3; ++k) out[3 + k] = g.q[k];
+  return ORA_OK;
+}
+
 int ora_set_wall_velocity(ora_sim* s, int32_t wall_id, const double vel[3]) {
   if (!s || !vel || wall_id < 0 || wall_id >= s->nw) return ORA_EINVAL;
   if (s->n > 0) return ORA_ESTATE;
@@ -1094,6 +1427,24 @@ int ora_get_wall_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta
       pairs[2 * p + 1] = s->wpairs[p].w;
     }
     if (delta_t) memcpy(&delta_t[3 * p], s->wpairs[p].dt, sizeof(double) * 3);
+  }
+  return ORA_OK;
+}
+
+int ora_get_mesh_contacts(ora_sim* s, int64_t cap, int64_t* triples, double* delta_t,
+                          int64_t* n_out) {
+  if (!s || cap < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  if (n_out) *n_out = s->nmpairs;
+  if (cap < s->nmpairs) return ORA_EINVAL;
+  for (int64_t p = 0; p < s->nmpairs; ++p) {
+    if (triples) {
+      const ora_mpair* M = &s->mpairs[p];
+      triples[3 * p] = M->i;
+      triples[3 * p + 1] = M->w;
+      triples[3 * p + 2] = M->tri - s->walls[M->w].tri_begin;
+    }
+    if (delta_t) memcpy(&delta_t[3 * p], s->mpairs[p].dt, sizeof(double) * 3);
   }
   return ORA_OK;
 }

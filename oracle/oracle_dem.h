@@ -70,6 +70,14 @@ int ora_add_cylinder(ora_sim* s, const double axis_point[3], const double axis_d
 int ora_add_cone(ora_sim* s, const double axis_point[3], const double axis_dir[3],
                  double radius0, double slope, double s_min, double s_max, int32_t inside,
                  int32_t material, double omega, double t_on, double t_off, int32_t* wall_id);
+/* Mesh wall: n_triangles triangles over n_vertices corners (x, y, z each);
+   triangles holds three corner indices per triangle, ordered so that
+   (p1 - p0) x (p2 - p0) points to the particles' side.  Surface velocity
+   omega x (x_c - axis_point) (NULL = none; axis_point NULL = first vertex).
+   Particle-face, particle-edge and particle-vertex contacts. */
+int ora_add_mesh(ora_sim* s, int64_t n_vertices, const double* vertices, int64_t n_triangles,
+                 const int32_t* triangles, int32_t material, const double axis_point[3],
+                 const double omega[3], double t_on, double t_off, int32_t* wall_id);
 /* Constant translational velocity of a wall (before the particles are set):
    its point and rotation axis move with it. */
 int ora_set_wall_velocity(ora_sim* s, int32_t wall_id, const double vel[3]);
@@ -84,7 +92,15 @@ int ora_get_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
                      uint8_t* touching, int64_t* n_out);
 int ora_get_wall_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
                           int64_t* n_out);
+/* particle-triangle candidates of mesh walls: (gid, wall id, triangle index
+   within the wall) triples and their tangential overlaps, sorted */
+int ora_get_mesh_contacts(ora_sim* s, int64_t cap, int64_t* triples, double* delta_t,
+                          int64_t* n_out);
 int ora_search_params(ora_sim* s, double* out4 /* d_max, r_s, h, skin */);
+/* Closest point of the triangle corners[0..2] to x (unit pin): out[0] = 0
+   face, 1 + a edge (a, a + 1), 4 + a corner a; out[1] signed distance from
+   the plane; out[2] squared distance; out[3..5] the point. */
+int ora_triangle_closest(const double corners[9], const double x[3], double out[6]);
 
 /* O(n^2) reference of the candidate set: all active pairs gid_i < gid_j with
    |x_j - x_i|^2 < r_s^2, sorted.  For the brute-force pin only. */

@@ -19,7 +19,10 @@ Scene dictionary layout::
                dict(kind="cylinder", axis_point, axis_dir, radius, s_min, s_max,
                     inside, material, omega, t_on, t_off) |
                dict(kind="cone", axis_point, axis_dir, radius0, slope, s_min, s_max,
-                    inside, material, omega, t_on, t_off), ...],
+                    inside, material, omega, t_on, t_off) |
+               dict(kind="mesh", vertices (m,3), triangles (k,3), material,
+                    axis_point=None, omega=None, t_on, t_off), ...],
+     every wall may carry velocity=(vx, vy, vz) (translation, None = fixed)
      "particles": {pos (n,3), radius (n,), vel (n,3), omega (n,3), types (n,)}}
 """
 from __future__ import annotations
@@ -84,6 +87,81 @@ def cone(axis_point, axis_dir, radius0, slope, s_min, s_max, inside=True, materi
                 radius0=float(radius0), slope=float(slope), s_min=float(s_min),
                 s_max=float(s_max), inside=bool(inside), material=material,
                 omega=float(omega), t_on=t_on, t_off=t_off, velocity=_vel(velocity))
+
+
+def mesh(vertices, triangles, material=0, axis_point=None, omega=None, t_on=-INF, t_off=INF,
+         velocity=None):
+    """Triangle-mesh wall: corners (m, 3) and corner indices (k, 3), each
+    triangle ordered so that (p1 - p0) x (p2 - p0) points to the particles."""
+    return dict(kind="mesh", vertices=np.ascontiguousarray(vertices, dtype=np.float64),
+                triangles=np.ascontiguousarray(triangles, dtype=np.int32), material=material,
+                axis_point=None if axis_point is None else tuple(axis_point),
+                omega=None if omega is None else tuple(omega), t_on=t_on, t_off=t_off,
+                velocity=_vel(velocity))
+
+
+def box_mesh(lo, hi, material=0, divisions=1):
+    """The inside of the box [lo, hi] as a closed triangle mesh (normals
+    inwards), each face split into divisions x divisions squares of two
+    triangles."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    verts, index, tris = [], {}, []
+
+    def vid(p):
+        key = tuple(np.round(p, 15))
+        if key not in index:
+            index[key] = len(verts)
+            verts.append(p)
+        return index[key]
+
+    m = divisions
+    for ax in range(3):
+        a, b = (ax + 1) % 3, (ax + 2) % 3
+        for side, val in ((0, lo[ax]), (1, hi[ax])):
+            grid = {}
+            for i in range(m + 1):
+                for j in range(m + 1):
+                    p = np.empty(3)
+                    p[ax] = val
+                    p[a] = lo[a] + (hi[a] - lo[a]) * i / m
+                    p[b] = lo[b] + (hi[b] - lo[b]) * j / m
+                    grid[i, j] = vid(p)
+            for i in range(m):
+                for j in range(m):
+                    q = [grid[i, j], grid[i + 1, j], grid[i + 1, j + 1], grid[i, j + 1]]
+                    # e_a x e_b = e_ax: counter-clockwise faces +ax, the low side
+                    t1, t2 = (q[0], q[1], q[2]), (q[0], q[2], q[3])
+                    if side == 1:
+                        t1, t2 = t1[::-1], t2[::-1]
+                    tris += [t1, t2]
+    return mesh(np.array(verts), np.array(tris), material)
+
+
+def frustum_mesh(axis_point, radius0, slope, s_min, s_max, segments=48, rings=4, material=0,
+                 omega=0.0):
+    """Inside of a cone frustum around the z axis through axis_point
+    (radius radius0 + slope s at height s in [s_min, s_max]) as a triangle
+    mesh: `segments` corners around, `rings` + 1 rings, normals towards the
+    axis.  The polygonal surface lies inside the analytic one between its
+    corners."""
+    c = np.asarray(axis_point, dtype=np.float64)
+    verts, tris = [], []
+    for r in range(rings + 1):
+        sz = s_min + (s_max - s_min) * r / rings
+        rad = radius0 + slope * sz
+        for k in range(segments):
+            a = 2 * math.pi * k / segments
+            verts.append(c + np.array([rad * math.cos(a), rad * math.sin(a), sz]))
+    for r in range(rings):
+        for k in range(segments):
+            a0 = r * segments + k
+            a1 = r * segments + (k + 1) % segments
+            b0, b1 = a0 + segments, a1 + segments
+            # counter-clockwise seen from the axis
+            tris += [(a0, b0, a1), (a1, b0, b1)]
+    return mesh(np.array(verts), np.array(tris), material,
+                axis_point=tuple(c), omega=(0.0, 0.0, float(omega)))
 
 
 def box_walls(lo, hi, material=0):
