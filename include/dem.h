@@ -175,6 +175,31 @@ int dem_add_cone_wall(dem_ctx* ctx, int32_t instance, const double axis_point[3]
                       double s_max, int32_t inside, int32_t material, double omega, double t_on,
                       double t_off, int32_t* wall_id);
 
+/* Mesh wall: a rigid surface of n_triangles triangles over n_vertices
+   corners (vertices: n_vertices x 3 doubles; triangles: n_triangles x 3
+   corner indices, each triangle ordered so that (p1 - p0) x (p2 - p0) points
+   to the particles' side).  Sec. 3.7: particles collide with the boundary's
+   faces, lines (edges) and points (vertices).  Every triangle whose plane
+   the centre is less than R behind and which is closer than R + skin at a
+   contact search is a candidate (at most 8 per particle, else DEM_ECAPACITY:
+   triangles should not be much smaller than the spheres).  At each step a
+   face touches when the centre projects strictly inside it and is less
+   than R above its plane; an edge or a vertex touches when it is the
+   closest point of every candidate triangle around it (a local minimum of
+   the distance over the surface) and closer than R; each contact acts once,
+   with the law of Sec. 2.1 and the wall as a body of infinite mass and
+   radius.  Surface velocity omega x (x_c - axis_point) (NULL omega = none;
+   NULL axis_point = the first vertex); translation with dem_set_wall_motion;
+   active for t_on <= t < t_off.  At most 2^24 triangles per instance;
+   DEM_EINVAL for out-of-range corner indices, degenerate triangles or
+   non-finite corners.  The arrays are copied.  Walls are added before
+   dem_set_particles (else DEM_ESTATE).  dem_restore does not support
+   contexts with mesh walls. */
+int dem_add_mesh_wall(dem_ctx* ctx, int32_t instance, int64_t n_vertices,
+                      const double* vertices, int64_t n_triangles, const int32_t* triangles,
+                      int32_t material, const double axis_point[3], const double omega[3],
+                      double t_on, double t_off, int32_t* wall_id);
+
 /* Translational motion of wall `wall_id` of an instance (Sec. 3.7, boundary
    motion: boundaries may rotate or translate): the wall moves with constant
    velocity `velocity` (3 doubles, m/s), so that at time t its point and its
@@ -273,9 +298,14 @@ int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque
    exceeds cap nothing else is written and DEM_EINVAL is returned. */
 int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                      double* delta_t, uint8_t* touching, int64_t* n_out);
-/* Particle-wall candidates as (gid, wall_id), sorted, with their tangential
-   overlaps.  Same capacity rule. */
+/* Particle-wall candidates of the analytic walls as (gid, wall_id), sorted,
+   with their tangential overlaps.  Same capacity rule. */
 int dem_get_wall_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
+                          double* delta_t, int64_t* n_out);
+/* Particle-triangle candidates of the mesh walls as (gid, wall_id,
+   triangle index within the wall) triples, sorted, with the tangential
+   overlap kept in each candidate's slot.  Same capacity rule. */
+int dem_get_mesh_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* triples,
                           double* delta_t, int64_t* n_out);
 
 /* Re-sort particles into cells and rebuild the contact lists at the current

@@ -47,10 +47,19 @@ int set_err(int code, const char* fmt, ...) {
 // Host-side description of one instance: materials, walls, the particles
 // given to dem_set_particles (kept until the batch is built on the device)
 // and the search geometry derived from them.
+// One triangle of a mesh wall as given: corners and the mesh's corner
+// indices; `wall` is the wall's index within its instance.
+struct HostTri {
+  double p[3][3];
+  int v[3];
+  int wall;
+};
+
 struct Instance {
   dem_material mat[kMaxTypes]{};
   bool mat_set[kMaxTypes]{};
   std::vector<WallDev> walls;
+  std::vector<HostTri> tris;  // triangles of the mesh walls, in wall order
   bool staged = false;
   bool own_domain = false;
   double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
@@ -94,6 +103,15 @@ struct dem_ctx {
   double4* xref = nullptr;
   int* wid[2]{};
   double* whist[2]{};
+  // mesh walls (all null without any): triangle table, grids, candidates
+  bool has_mesh = false;
+  TriDev* d_tri = nullptr;
+  int* d_mcell = nullptr;
+  int* d_mcell_tri = nullptr;
+  int* mtri[2]{};
+  double* mhist[2]{};
+  double4 *Fm = nullptr, *Tm = nullptr;
+  std::vector<int> tri_wall, tri_local;  // per global triangle: instance wall, index in it
   int* nbr[2]{};
   double* hist[2]{};
   int* rowlen[2]{};
@@ -202,6 +220,12 @@ void free_particles(dem_ctx* c) {
   c->alloc_bytes.clear();
   c->dev_bytes = 0;
   c->d_mort = nullptr;
+  c->has_mesh = false;
+  c->d_tri = nullptr;
+  c->d_mcell = c->d_mcell_tri = nullptr;
+  c->mtri[0] = c->mtri[1] = nullptr;
+  c->mhist[0] = c->mhist[1] = nullptr;
+  c->Fm = c->Tm = nullptr;
   c->ready = false;
   c->n = 0;
 }
@@ -276,6 +300,8 @@ PairCoef make_coef(const dem_config& cfg, double Ye, double Ge, double e, double
 ParticleBufs pbufs(dem_ctx* c, int k) { return ParticleBufs{c->pos[k], c->vel[k], c->omg[k]}; }
 NbrList nlist(dem_ctx* c, int k) { return NbrList{c->nbr[k], c->hist[k], c->rowlen[k], c->cap}; }
 WallSlots wslots(dem_ctx* c, int k) { return WallSlots{c->wid[k], c->whist[k]}; }
+MeshSlots mslots(dem_ctx* c, int k) { return MeshSlots{c->mtri[k], c->mhist[k]}; }
+MeshTables mtables(dem_ctx* c) { return MeshTables{c->d_tri, c->d_mcell, c->d_mcell_tri}; }
 
 // Contact search: counting sort into cells, reorder, particle-wall search and
 // particle-pair search with history carry-over.  Flips both parities.  The
@@ -294,7 +320,8 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
                         c->gid[p],
                         c->gid[p ^ 1],
                         c->info[p], c->info[p ^ 1], c->xref, wslots(c, p), wslots(c, p ^ 1),
-                        c->d_walls, move_forces ? c->F[p] : nullptr,
+                        c->d_walls, mtables(c), mslots(c, p), mslots(c, p ^ 1),
+                        move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
                         c->d_clock, step_rel, c->d_flags, s));
   HIPCHK(launch_search(c->d_inst, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
@@ -307,10 +334,15 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
 
 int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* drift = nullptr) {
   const int a = c->cur, p = c->pcur;
+  if (c->has_mesh)
+    HIPCHK(launch_mesh(c->cfg.precision, c->sp, c->d_pw, c->d_walls, mtables(c), pbufs(c, a),
+                       c->info[p], mslots(c, p), c->Fm, c->Tm, c->d_clock, step_rel,
+                       c->d_flags, c->stream));
   HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_inst, c->d_pp, c->d_pw, c->d_walls,
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
-                      c->d_clock, step_rel, c->d_flags, drift, c->force_block, c->stream));
+                      c->d_clock, step_rel, c->d_flags, drift, c->Fm, c->Tm, c->force_block,
+                      c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }
@@ -591,12 +623,13 @@ int read_flags(dem_ctx* c, int* flags) {
 int flags_to_error(dem_ctx* c, int flags) {
   if (flags == 0) return DEM_OK;
   c->failed = true;
-  if (flags & (kFlagNbrOverflow | kFlagWallOverflow)) {
+  if (flags & (kFlagNbrOverflow | kFlagWallOverflow | kFlagMeshOverflow)) {
     c->fail_code = DEM_ECAPACITY;
     return set_err(DEM_ECAPACITY,
-                   "capacity exceeded (flags 0x%x): more than %d neighbours or %d wall "
-                   "contacts for a particle; raise max_neighbors",
-                   flags, c->max_nb, kWallSlots);
+                   "capacity exceeded (flags 0x%x): more than %d neighbours, %d wall "
+                   "contacts or %d triangle candidates for a particle; raise max_neighbors "
+                   "or use larger mesh triangles",
+                   flags, c->max_nb, kWallSlots, kMeshSlots);
   }
   c->fail_code = DEM_EUNSTABLE;
   if (flags & kFlagNonFinite)
@@ -641,6 +674,104 @@ int snapshot(dem_ctx* c, HostSnapshot& h, bool want_pos, bool want_vel, bool wan
 }
 
 int commit(dem_ctx* c);
+
+// Triangle table and grids of the mesh walls of every instance.  Each mesh
+// gets a uniform grid over its bounding box at time 0 grown by the largest
+// reach of a candidate (largest radius + skin), every triangle listed in
+// the cells its own grown box overlaps (ascending triangle order), so that
+// the cell of a particle centre lists every triangle that can be its
+// candidate.  Sets the mesh fields of the instances' walls.
+void build_meshes(dem_ctx* c, std::vector<TriDev>* htri, std::vector<int>* hcell,
+                  std::vector<int>* hcell_tri) {
+  c->tri_wall.clear();
+  c->tri_local.clear();
+  for (Instance& I : c->inst) {
+    const double reach = (0.5 * I.dmax + I.skin) * (1.0 + 1e-9);
+    int64_t t0 = 0;
+    for (size_t wl = 0; wl < I.walls.size(); ++wl) {
+      WallDev& W = I.walls[wl];
+      if (W.kind != 3) continue;
+      const int gw = I.w_begin + (int)wl;
+      W.tri_begin = (int)htri->size();
+      double lo[3] = {HUGE_VAL, HUGE_VAL, HUGE_VAL}, hi[3] = {-HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+      double ext = 0.0;
+      int cnt = 0;
+      while (t0 < (int64_t)I.tris.size() && I.tris[(size_t)t0].wall == (int)wl) {
+        const HostTri& h = I.tris[(size_t)t0];
+        TriDev T;
+        memset(&T, 0, sizeof(T));
+        for (int cc = 0; cc < 3; ++cc) {
+          const int c1 = cc == 2 ? 0 : cc + 1;
+          for (int k = 0; k < 3; ++k) {
+            T.p[cc][k] = h.p[cc][k];
+            T.e[cc][k] = h.p[c1][k] - h.p[cc][k];
+          }
+          T.v[cc] = h.v[cc];
+        }
+        const double e01[3] = {h.p[1][0] - h.p[0][0], h.p[1][1] - h.p[0][1], h.p[1][2] - h.p[0][2]};
+        const double e02[3] = {h.p[2][0] - h.p[0][0], h.p[2][1] - h.p[0][1], h.p[2][2] - h.p[0][2]};
+        const double N[3] = {e01[1] * e02[2] - e01[2] * e02[1], e01[2] * e02[0] - e01[0] * e02[2],
+                             e01[0] * e02[1] - e01[1] * e02[0]};
+        const double len = sqrt((N[0] * N[0] + N[1] * N[1]) + N[2] * N[2]);
+        for (int k = 0; k < 3; ++k) T.n[k] = N[k] / len;
+        T.wall = gw;
+        double tlo[3], thi[3];
+        for (int k = 0; k < 3; ++k) {
+          tlo[k] = std::min(h.p[0][k], std::min(h.p[1][k], h.p[2][k]));
+          thi[k] = std::max(h.p[0][k], std::max(h.p[1][k], h.p[2][k]));
+          lo[k] = std::min(lo[k], tlo[k]);
+          hi[k] = std::max(hi[k], thi[k]);
+          ext = std::max(ext, thi[k] - tlo[k]);
+        }
+        c->tri_wall.push_back((int)wl);
+        c->tri_local.push_back(cnt);
+        htri->push_back(T);
+        ++cnt;
+        ++t0;
+      }
+      W.tri_count = cnt;
+      // grid: cells no smaller than the reach nor than the largest triangle,
+      // at most about four per triangle
+      double mh = std::max(reach, ext);
+      if (!(mh > 0.0)) mh = 1.0;
+      int64_t nc[3];
+      for (;;) {
+        int64_t tot = 1;
+        for (int k = 0; k < 3; ++k) {
+          W.mlo[k] = lo[k] - reach;
+          nc[k] = std::max<int64_t>(1, (int64_t)ceil((hi[k] + reach - W.mlo[k]) / mh));
+          tot *= nc[k];
+        }
+        if (tot <= 4 * (int64_t)cnt + 1024) break;
+        mh *= 1.5;
+      }
+      W.mh = mh;
+      for (int k = 0; k < 3; ++k) W.mnc[k] = (int)nc[k];
+      const int64_t ncell = nc[0] * nc[1] * nc[2];
+      std::vector<std::vector<int>> lists((size_t)ncell);
+      for (int f = W.tri_begin; f < W.tri_begin + cnt; ++f) {
+        const TriDev& T = (*htri)[(size_t)f];
+        int64_t a[3], b[3];
+        for (int k = 0; k < 3; ++k) {
+          const double tl = std::min(T.p[0][k], std::min(T.p[1][k], T.p[2][k])) - reach;
+          const double th = std::max(T.p[0][k], std::max(T.p[1][k], T.p[2][k])) + reach;
+          a[k] = std::max<int64_t>(0, (int64_t)floor((tl - W.mlo[k]) / mh) - 1);
+          b[k] = std::min<int64_t>(nc[k] - 1, (int64_t)floor((th - W.mlo[k]) / mh) + 1);
+        }
+        for (int64_t z = a[2]; z <= b[2]; ++z)
+          for (int64_t y = a[1]; y <= b[1]; ++y)
+            for (int64_t x = a[0]; x <= b[0]; ++x)
+              lists[(size_t)(x + nc[0] * (y + nc[1] * z))].push_back(f);
+      }
+      W.cell_base = (int)hcell->size();
+      for (int64_t q = 0; q < ncell; ++q) {
+        hcell->push_back((int)hcell_tri->size());
+        for (int f : lists[(size_t)q]) hcell_tri->push_back(f);
+      }
+      hcell->push_back((int)hcell_tri->size());
+    }
+  }
+}
 
 // Translating walls: a wall may move at most half the skin between two
 // searches, the particles' displacement guard taking the other half, so that
@@ -855,6 +986,9 @@ int commit(dem_ctx* c) {
     int rc = plan_grids(c, c->cfg.cell_factor, &total_keys, &mort_total);
     if (rc) return rc;
   }
+  std::vector<TriDev> htri;
+  std::vector<int> hcell, hcell_tri;
+  build_meshes(c, &htri, &hcell, &hcell_tri);
   c->dynamic = c->cfg.rebuild_interval == 0;
   double ihs_max = 0.0, rate0 = 0.0, ihs_min = HUGE_VAL;
   bool all_skins = true;
@@ -943,6 +1077,18 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
   rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
+  if (!htri.empty()) {
+    rc = rc ? rc : dalloc_t(c, &c->d_tri, htri.size());
+    rc = rc ? rc : dalloc_t(c, &c->d_mcell, hcell.size());
+    rc = rc ? rc : dalloc_t(c, &c->d_mcell_tri, std::max<size_t>(hcell_tri.size(), 1));
+    for (int b = 0; b < 2; ++b) {
+      rc = rc ? rc : dalloc_t(c, &c->mtri[b], NN * kMeshSlots);
+      rc = rc ? rc : dalloc_t(c, &c->mhist[b], NN * kMeshSlots * 3);
+    }
+    rc = rc ? rc : dalloc_t(c, &c->Fm, NN);
+    rc = rc ? rc : dalloc_t(c, &c->Tm, NN);
+    c->has_mesh = rc == DEM_OK;
+  }
   if (rc == DEM_OK) {
     hipError_t he = hipHostMalloc((void**)&c->h_drift,
                                   sizeof(unsigned long long) * kDriftSpread * (kDynChunk + 1),
@@ -1025,6 +1171,17 @@ int commit(dem_ctx* c) {
   if (!hwalls.empty())
     HIPCHK(hipMemcpyAsync(c->d_walls, hwalls.data(), hwalls.size() * sizeof(WallDev),
                           hipMemcpyHostToDevice, s));
+  if (c->has_mesh) {
+    HIPCHK(hipMemcpyAsync(c->d_tri, htri.data(), htri.size() * sizeof(TriDev),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_mcell, hcell.data(), hcell.size() * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+    if (!hcell_tri.empty())
+      HIPCHK(hipMemcpyAsync(c->d_mcell_tri, hcell_tri.data(), hcell_tri.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    HIPCHK(launch_fill_i32(c->mtri[0], -1, (int64_t)NN * kMeshSlots, s));
+    HIPCHK(launch_fill_i32((int*)c->mhist[0], 0, (int64_t)NN * kMeshSlots * 6, s));
+  }
   c->cur = 0;
   c->pcur = 0;
   if (N > 0) {
@@ -1251,6 +1408,117 @@ int dem_add_cone_wall(dem_ctx* c, int32_t instance, const double axis_point[3],
   W.t_off = t_off;
   if (wall_id) *wall_id = (int32_t)I.walls.size();
   I.walls.push_back(W);
+  return DEM_OK;
+}
+
+int dem_add_mesh_wall(dem_ctx* c, int32_t instance, int64_t n_vertices, const double* vertices,
+                      int64_t n_triangles, const int32_t* triangles, int32_t material,
+                      const double axis_point[3], const double omega[3], double t_on,
+                      double t_off, int32_t* wall_id) {
+  if (!c || !vertices || !triangles) return set_err(DEM_EINVAL, "null argument");
+  if (int rc = check_instance(c, instance)) return rc;
+  Instance& I = c->inst[(size_t)instance];
+  if ((int)I.walls.size() >= kMaxWalls) return set_err(DEM_EINVAL, "at most 32 walls");
+  if (material < 0 || material >= kMaxTypes || !I.mat_set[material])
+    return set_err(DEM_EINVAL, "wall material %d not set", material);
+  if (I.staged) return set_err(DEM_ESTATE, "walls are added before dem_set_particles");
+  if (n_vertices < 3 || n_vertices > ((int64_t)1 << 30))
+    return set_err(DEM_EINVAL, "n_vertices must be in [3, 2^30]");
+  if (n_triangles < 1 || (int64_t)I.tris.size() + n_triangles > kMaxMeshTriangles)
+    return set_err(DEM_EINVAL, "1 to %d triangles per instance", kMaxMeshTriangles);
+  for (int64_t k = 0; k < 3 * n_vertices; ++k)
+    if (!std::isfinite(vertices[k])) return set_err(DEM_EINVAL, "non-finite vertex");
+  const int wl = (int)I.walls.size();
+  std::vector<HostTri> add((size_t)n_triangles);
+  for (int64_t f = 0; f < n_triangles; ++f) {
+    HostTri& h = add[(size_t)f];
+    h.wall = wl;
+    for (int cc = 0; cc < 3; ++cc) {
+      const int32_t v = triangles[3 * f + cc];
+      if (v < 0 || v >= n_vertices)
+        return set_err(DEM_EINVAL, "triangle %lld: corner index out of range", (long long)f);
+      h.v[cc] = v;
+      for (int k = 0; k < 3; ++k) h.p[cc][k] = vertices[3 * (int64_t)v + k];
+    }
+    const double e01[3] = {h.p[1][0] - h.p[0][0], h.p[1][1] - h.p[0][1], h.p[1][2] - h.p[0][2]};
+    const double e02[3] = {h.p[2][0] - h.p[0][0], h.p[2][1] - h.p[0][1], h.p[2][2] - h.p[0][2]};
+    const double N[3] = {e01[1] * e02[2] - e01[2] * e02[1], e01[2] * e02[0] - e01[0] * e02[2],
+                         e01[0] * e02[1] - e01[1] * e02[0]};
+    const double len = sqrt((N[0] * N[0] + N[1] * N[1]) + N[2] * N[2]);
+    if (!(len > 0.0) || !std::isfinite(len))
+      return set_err(DEM_EINVAL, "triangle %lld is degenerate", (long long)f);
+  }
+  WallDev W;
+  memset(&W, 0, sizeof(W));
+  W.kind = 3;
+  for (int k = 0; k < 3; ++k) {
+    W.p[k] = vertices[k];
+    W.ax[k] = axis_point ? axis_point[k] : vertices[k];
+    W.omega[k] = omega ? omega[k] : 0.0;
+  }
+  W.material = material;
+  W.t_on = t_on;
+  W.t_off = t_off;
+  I.tris.insert(I.tris.end(), add.begin(), add.end());
+  if (wall_id) *wall_id = wl;
+  I.walls.push_back(W);
+  return DEM_OK;
+}
+
+int dem_get_mesh_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* triples,
+                          double* delta_t, int64_t* n_out) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
+  if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
+  if (!c->has_mesh) {
+    if (n_out) *n_out = 0;
+    return DEM_OK;
+  }
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> tr(n * kMeshSlots);
+  std::vector<double> th(n * kMeshSlots * 3);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(tr.data(), c->mtri[c->pcur], tr.size() * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(th.data(), c->mhist[c->pcur], th.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  struct Rec {
+    int64_t i, tri;
+    double d[3];
+  };
+  std::vector<Rec> out;
+  const Instance& In = c->inst[(size_t)instance];
+  for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    for (int sl = 0; sl < kMeshSlots; ++sl) {
+      const int t = tr[(size_t)sl * n + p];
+      if (t < 0) break;
+      Rec r;
+      r.i = h.gid[p] - In.p_begin;
+      r.tri = t;
+      for (int k = 0; k < 3; ++k) r.d[k] = th[(size_t)(3 * sl + k) * n + p];
+      out.push_back(r);
+    }
+  }
+  std::sort(out.begin(), out.end(),
+            [](const Rec& a, const Rec& b) { return a.i != b.i ? a.i < b.i : a.tri < b.tri; });
+  if (n_out) *n_out = (int64_t)out.size();
+  if ((int64_t)out.size() > cap)
+    return set_err(DEM_EINVAL, "cap %lld < %zu mesh contacts", (long long)cap, out.size());
+  for (size_t m = 0; m < out.size(); ++m) {
+    if (triples) {
+      triples[3 * m] = out[m].i;
+      triples[3 * m + 1] = c->tri_wall[(size_t)out[m].tri];
+      triples[3 * m + 2] = c->tri_local[(size_t)out[m].tri];
+    }
+    if (delta_t)
+      for (int k = 0; k < 3; ++k) delta_t[3 * m + k] = out[m].d[k];
+  }
   return DEM_OK;
 }
 
@@ -1567,6 +1835,8 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
   if (int rc = check_instance(c, instance)) return rc;
   if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
   if (n_pairs < 0 || n_wall < 0) return set_err(DEM_EINVAL, "negative count");
+  if (c->has_mesh)
+    return set_err(DEM_EINVAL, "restoring contacts with mesh walls is not supported");
   if ((n_pairs > 0 && (!pairs || !delta_t)) || (n_wall > 0 && (!wall_pairs || !wall_delta_t)))
     return set_err(DEM_EINVAL, "null array");
   if (int rc = wait_user(c)) return rc;

@@ -10,6 +10,7 @@ namespace demgpu {
 constexpr int kMaxTypes = 16;
 constexpr int kMaxWalls = 32;
 constexpr int kWallSlots = 4;   // particle-wall contacts kept per particle
+constexpr int kMeshSlots = 8;   // particle-triangle candidates kept per particle
 constexpr int kBlock = 256;     // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr int kTypeMask = 0xffff;
@@ -17,6 +18,7 @@ constexpr int kInactive = 1 << 16;  // flag bit in the per-particle info word
 constexpr int kInstShift = 20;      // info bits 20..30: instance of the particle
 constexpr int kDriftSpread = 32;  // words per drift record
 constexpr int kMaxInstances = 2048;
+constexpr int kMaxMeshTriangles = 1 << 24;  // per instance
 
 // Sticky error bits raised by kernels (read once per dem_step call).
 enum : int {
@@ -24,6 +26,7 @@ enum : int {
   kFlagNonFinite = 2,     // NaN/Inf in the state
   kFlagNbrOverflow = 4,   // a particle had more candidate neighbours than max_nb
   kFlagWallOverflow = 8,  // more wall candidates than kWallSlots
+  kFlagMeshOverflow = 16, // more triangle candidates than kMeshSlots
 };
 
 // Per material pair constants of the Hertz-Mindlin law (effective-parameter
@@ -39,11 +42,12 @@ struct PairCoef {
   double kn, kt, en, et, mu, mur, pad0, pad1;
 };
 
-// Analytic wall.  kind 0: plane (point p, unit normal nrm into the domain,
-// optional rectangular extent along u / vax).  kind 2: cone, as the cylinder
-// with the surface at radius + slope s.  kind 1: cylinder (axis point p,
-// unit axis nrm, radius, axial range [smin, smax], particles inside or
-// outside).  Translation with velocity vel: at time t the point and the
+// Wall.  kind 0: plane (point p, unit normal nrm into the domain, optional
+// rectangular extent along u / vax).  kind 2: cone, as the cylinder with the
+// surface at radius + slope s.  kind 1: cylinder (axis point p, unit axis
+// nrm, radius, axial range [smin, smax], particles inside or outside).
+// kind 3: triangle mesh (its triangles in the triangle table, found through
+// a uniform grid over the mesh at time 0; p is its first corner).  Translation with velocity vel: at time t the point and the
 // rotation axis sit at p + vel t and ax + vel t.  Surface velocity at a
 // contact point x_c: vel + omega x (x_c - ax(t)).  Active for t_on <= t < t_off.
 struct WallDev {
@@ -56,6 +60,39 @@ struct WallDev {
   double slope, q;  // cone: radius + slope s at axial coordinate s; q = sqrt(1 + slope^2)
   double vel[3];
   double axo[3];  // ax - p: the rotation axis moves with the wall
+  // mesh: triangles [tri_begin, tri_begin + tri_count); grid cell (cx, cy,
+  // cz) = floor((x - vel t - mlo) / mh) lists its triangles at
+  // cell_tri[cell[cell_base + c] .. cell[cell_base + c + 1]), c = cx + mnc0
+  // (cy + mnc1 cz)
+  int tri_begin, tri_count, cell_base, pad;
+  int mnc[3], pad2;
+  double mlo[3], mh;
+};
+
+// One triangle of a mesh wall: corners at time 0 (the particles' side is the
+// side of (p1 - p0) x (p2 - p0)), edge vectors e_c = p_{c+1} - p_c, unit
+// normal, the mesh's own corner indices (names of its edges and vertices)
+// and the owning wall.
+struct TriDev {
+  double p[3][3];
+  double e[3][3];
+  double n[3];
+  int v[3];
+  int wall;
+};
+
+// Particle-triangle candidates: slot s of particle i at s * n + i (global
+// triangle index or -1), tangential overlaps in 3 * kMeshSlots planes.
+struct MeshSlots {
+  int* tri;
+  double* hist;
+};
+
+// Triangle table and mesh grids (all null when no instance has a mesh).
+struct MeshTables {
+  const TriDev* tri;
+  const int* cell;
+  const int* cell_tri;
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).
@@ -141,13 +178,14 @@ hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const in
 hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
                             const int* start, const int* gid, int* perm, hipStream_t s);
 // perm: new -> old index; inv receives old -> new
-// The particle-wall search takes the walls where they are at time
-// (*clock + step_rel) dt.
+// The particle-wall and particle-triangle searches take the walls where they
+// are at time (*clock + step_rel) dt.
 hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
                           ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
+                          MeshTables mt, MeshSlots ms_src, MeshSlots ms_dst,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
                           hipStream_t s);
@@ -159,13 +197,22 @@ hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double
 // kick of this step, first half kick and drift of the next), 1 = velocity
 // Verlet last step of a call (second half kick, forces stored), 2 = explicit
 // Euler (forces at the current state, then the update; forces stored).
+// Fx / Tx (may be null): further force and torque per particle, added to the
+// contact sums (the mesh contacts of the same state).
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
                         const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, int block,
-                        hipStream_t s);
+                        const int* flags, unsigned long long* drift, const double4* Fx,
+                        const double4* Tx, int block, hipStream_t s);
+// Contacts of every particle with mesh walls at time (*clock + step_rel) dt,
+// from its triangle candidates (tangential overlaps updated): force and
+// torque per particle into Fm / Tm (zero without contacts).
+hipError_t launch_mesh(int precision, const StepParams& sp, const PairCoef* pw,
+                       const WallDev* walls, MeshTables mt, ParticleBufs in, const int* info,
+                       MeshSlots ms, double4* Fm, double4* Tm, const int64_t* clock,
+                       int64_t step_rel, const int* flags, hipStream_t s);
 // first half kick + drift from stored forces (start of a velocity-Verlet call).
 // When drift is not null, both launchers raise the kDriftSpread words at
 // drift (as the bits of non-negative doubles) so that their maximum is the

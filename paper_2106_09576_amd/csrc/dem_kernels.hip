@@ -357,6 +357,83 @@ __device__ inline void wall_geo(const WallDev& W, const double x[3], double R, d
   }
 }
 
+// ------------------------------------------------------------ mesh walls
+
+// Closest point of the closed triangle T, moved by vel t, to the point x: the
+// projection onto the triangle's plane when it lies strictly inside all
+// three edges (a face), else the closest of the three edges' own closest
+// points (the projection onto the edge line clamped to the edge), on an edge
+// when strictly inside it and on a corner otherwise.  s is the signed
+// distance from the plane along the unit normal, d2 the squared distance.
+struct TriGeo {
+  int feature;  // 0 face, 1 edge (corners a, b = a + 1 mod 3), 2 vertex (corner a)
+  int a, b;
+  double s, d2;
+  double q[3];
+};
+
+__device__ inline void cross3(const double* a, const double* b, double* r) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ inline void tri_closest(const TriDev& T, const double vel[3], double t,
+                                   const double x[3], TriGeo& g) {
+  double P[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P[c][k] = T.p[c][k] + vel[k] * t;
+  const double rel[3] = {x[0] - P[0][0], x[1] - P[0][1], x[2] - P[0][2]};
+  g.s = dot3(rel, T.n);
+  bool inside = true;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double r[3] = {x[0] - P[c][0], x[1] - P[c][1], x[2] - P[c][2]};
+    double cr[3];
+    cross3(T.e[c], r, cr);
+    if (!(dot3(cr, T.n) > 0.0)) inside = false;
+  }
+  if (inside) {
+    g.feature = 0;
+    g.a = g.b = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) g.q[k] = x[k] - g.s * T.n[k];
+    g.d2 = g.s * g.s;
+    return;
+  }
+  g.d2 = INFINITY;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double* E = T.e[c];
+    const double r[3] = {x[0] - P[c][0], x[1] - P[c][1], x[2] - P[c][2]};
+    const double u = dot3(r, E) / dot3(E, E);
+    const double uc = u <= 0.0 ? 0.0 : (u >= 1.0 ? 1.0 : u);
+    const double q[3] = {P[c][0] + uc * E[0], P[c][1] + uc * E[1], P[c][2] + uc * E[2]};
+    const double dq[3] = {x[0] - q[0], x[1] - q[1], x[2] - q[2]};
+    const double d2 = dot3(dq, dq);
+    if (d2 < g.d2) {
+      g.d2 = d2;
+      g.q[0] = q[0];
+      g.q[1] = q[1];
+      g.q[2] = q[2];
+      const int c1 = c == 2 ? 0 : c + 1;
+      if (u <= 0.0) {
+        g.feature = 2;
+        g.a = g.b = c;
+      } else if (u >= 1.0) {
+        g.feature = 2;
+        g.a = g.b = c1;
+      } else {
+        g.feature = 1;
+        g.a = c;
+        g.b = c1;
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------------- reorder
 
 // Gather every particle array into sorted order, record the reference
@@ -368,6 +445,7 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
                           int* __restrict__ gid_dst, const int* __restrict__ info_src,
                           int* __restrict__ info_dst, double4* __restrict__ xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* __restrict__ walls,
+                          MeshTables mt, MeshSlots ms_src, MeshSlots ms_dst,
                           const double4* __restrict__ F_src, const double4* __restrict__ T_src,
                           double4* __restrict__ F_dst, double4* __restrict__ T_dst,
                           const int64_t* __restrict__ clock, int64_t step_rel,
@@ -395,6 +473,7 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
     const InstDev& I = inst[inf >> kInstShift];
     double x[3] = {ps.x, ps.y, ps.z};
     for (int w = I.wall_begin; w < I.wall_end; ++w) {
+      if (walls[w].kind == 3) continue;
       WallGeo g;
       wall_geo(walls[w], x, ps.w, I.skin, false, t, g);
       if (!g.candidate) continue;
@@ -421,20 +500,75 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
     }
   }
   for (; c < kWallSlots; ++c) ws_dst.wid[(int64_t)c * n + p] = -1;
+  if (!mt.tri) return;
+  // particle-triangle candidates: the triangles listed in the centre's cell
+  // of each mesh grid that lie less than R + skin away from it, with the
+  // centre less than R behind their plane; overlaps carried by triangle
+  int cm = 0;
+  if (!(inf & kInactive)) {
+    const InstDev& I = inst[inf >> kInstShift];
+    const double x[3] = {ps.x, ps.y, ps.z};
+    const double R = ps.w;
+    const double m = R + I.skin;
+    for (int w = I.wall_begin; w < I.wall_end && cm <= kMeshSlots; ++w) {
+      const WallDev& W = walls[w];
+      if (W.kind != 3) continue;
+      int c3[3];
+      bool in = true;
+      for (int k = 0; k < 3; ++k) {
+        const double u = (x[k] - W.vel[k] * t - W.mlo[k]) / W.mh;
+        if (!(u >= 0.0 && u < (double)W.mnc[k])) in = false;
+        c3[k] = in ? (int)u : 0;
+      }
+      if (!in) continue;
+      const int cb = W.cell_base + c3[0] + W.mnc[0] * (c3[1] + W.mnc[1] * c3[2]);
+      const int q1 = mt.cell[cb + 1];
+      for (int q = mt.cell[cb]; q < q1; ++q) {
+        const int tr = mt.cell_tri[q];
+        TriGeo g;
+        tri_closest(mt.tri[tr], W.vel, t, x, g);
+        if (!(g.s > -R && g.d2 < m * m)) continue;
+        if (cm == kMeshSlots) {
+          atomicOr(flags, kFlagMeshOverflow);
+          ++cm;
+          break;
+        }
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+        for (int s = 0; s < kMeshSlots; ++s) {
+          const int ot = ms_src.tri[(int64_t)s * n + o];
+          if (ot < 0) break;
+          if (ot == tr) {
+            h0 = ms_src.hist[(int64_t)(3 * s + 0) * n + o];
+            h1 = ms_src.hist[(int64_t)(3 * s + 1) * n + o];
+            h2 = ms_src.hist[(int64_t)(3 * s + 2) * n + o];
+            break;
+          }
+        }
+        ms_dst.tri[(int64_t)cm * n + p] = tr;
+        ms_dst.hist[(int64_t)(3 * cm + 0) * n + p] = h0;
+        ms_dst.hist[(int64_t)(3 * cm + 1) * n + p] = h1;
+        ms_dst.hist[(int64_t)(3 * cm + 2) * n + p] = h2;
+        ++cm;
+      }
+    }
+  }
+  for (int c2 = cm < kMeshSlots ? cm : kMeshSlots; c2 < kMeshSlots; ++c2)
+    ms_dst.tri[(int64_t)c2 * n + p] = -1;
 }
 
 hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
                           ParticleBufs src, ParticleBufs dst, const int* gid_src, int* gid_dst,
                           const int* info_src, int* info_dst, double4* xref,
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
+                          MeshTables mt, MeshSlots ms_src, MeshSlots ms_dst,
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
                           hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, perm, inv,
                      src, dst,
-                     gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, F_src,
-                     T_src, F_dst, T_dst, clock, step_rel, flags);
+                     gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, mt,
+                     ms_src, ms_dst, F_src, T_src, F_dst, T_dst, clock, step_rel, flags);
   return hipGetLastError();
 }
 
@@ -760,8 +894,42 @@ __device__ __forceinline__ void pp_contact<float>(const PairCoef& c, int rolling
   hm_law<float>(c, rolling, model, dt, dn, n, vij, wrel, vr, me, Re, Ri, dtl, Fi, Mi);
 }
 
-// Particle against wall W at time t, the wall acting as a body of infinite
-// mass and radius whose contact point moves with the wall's surface velocity.
+// The law against wall W, a body of infinite mass and radius whose contact
+// point moves with the wall's surface velocity: unit normal gn from the
+// particle to the wall, overlap gdn, lever arm of the contact point about the
+// wall's rotation axis.
+template <typename R>
+__device__ __forceinline__ void wall_law(const PairCoef& c, int rolling, int model, double dt,
+                                         const WallDev& W, const double gn[3], double gdn,
+                                         const double arm[3], double4 xi, double4 vi,
+                                         double4 wi, double dtl[3], double Fi[3],
+                                         double Mi[3]) {
+  const double dn = gdn < 0.0 ? 0.0 : gdn;
+  const double vw[3] = {W.vel[0] + (W.omega[1] * arm[2] - W.omega[2] * arm[1]),
+                        W.vel[1] + (W.omega[2] * arm[0] - W.omega[0] * arm[2]),
+                        W.vel[2] + (W.omega[0] * arm[1] - W.omega[1] * arm[0])};
+  const double Ri = xi.w;
+  const double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
+  const double vd[3] = {(vi.x - vw[0]) + (rw[1] * gn[2] - rw[2] * gn[1]),
+                        (vi.y - vw[1]) + (rw[2] * gn[0] - rw[0] * gn[2]),
+                        (vi.z - vw[2]) + (rw[0] * gn[1] - rw[1] * gn[0])};
+  const double wd[3] = {wi.x - W.omega[0], wi.y - W.omega[1], wi.z - W.omega[2]};
+  const R n[3] = {(R)gn[0], (R)gn[1], (R)gn[2]};
+  const R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
+  const R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
+  // rolling speed against a wall: |R_i (omega_i - Omega_wall) x n|
+  R vr = (R)0;
+  if (rolling == 2) {
+    const R rr[3] = {(R)Ri * wrel[0], (R)Ri * wrel[1], (R)Ri * wrel[2]};
+    const R vroll[3] = {rr[1] * n[2] - rr[2] * n[1], rr[2] * n[0] - rr[0] * n[2],
+                        rr[0] * n[1] - rr[1] * n[0]};
+    vr = Fast<R>::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2]);
+  }
+  const R me = Fast<R>::rcp((R)vi.w);
+  hm_law<R>(c, rolling, model, dt, (R)dn, n, vij, wrel, vr, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
+}
+
+// Particle against wall W at time t.
 template <typename R>
 __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int model, double dt,
                                            const WallDev& W, double skin, double t, double4 xi,
@@ -776,30 +944,7 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
     Mi[0] = Mi[1] = Mi[2] = 0.0;
     return;
   }
-  const double dn = g.dn < 0.0 ? 0.0 : g.dn;
-  const double* arm = g.arm;
-  const double vw[3] = {W.vel[0] + (W.omega[1] * arm[2] - W.omega[2] * arm[1]),
-                        W.vel[1] + (W.omega[2] * arm[0] - W.omega[0] * arm[2]),
-                        W.vel[2] + (W.omega[0] * arm[1] - W.omega[1] * arm[0])};
-  const double Ri = xi.w;
-  const double rw[3] = {Ri * wi.x, Ri * wi.y, Ri * wi.z};
-  const double vd[3] = {(vi.x - vw[0]) + (rw[1] * g.n[2] - rw[2] * g.n[1]),
-                        (vi.y - vw[1]) + (rw[2] * g.n[0] - rw[0] * g.n[2]),
-                        (vi.z - vw[2]) + (rw[0] * g.n[1] - rw[1] * g.n[0])};
-  const double wd[3] = {wi.x - W.omega[0], wi.y - W.omega[1], wi.z - W.omega[2]};
-  const R n[3] = {(R)g.n[0], (R)g.n[1], (R)g.n[2]};
-  const R vij[3] = {(R)vd[0], (R)vd[1], (R)vd[2]};
-  const R wrel[3] = {(R)wd[0], (R)wd[1], (R)wd[2]};
-  // rolling speed against a wall: |R_i (omega_i - Omega_wall) x n|
-  R vr = (R)0;
-  if (rolling == 2) {
-    const R rr[3] = {(R)Ri * wrel[0], (R)Ri * wrel[1], (R)Ri * wrel[2]};
-    const R vroll[3] = {rr[1] * n[2] - rr[2] * n[1], rr[2] * n[0] - rr[0] * n[2],
-                        rr[0] * n[1] - rr[1] * n[0]};
-    vr = Fast<R>::sqrt((vroll[0] * vroll[0] + vroll[1] * vroll[1]) + vroll[2] * vroll[2]);
-  }
-  const R me = Fast<R>::rcp((R)vi.w);
-  hm_law<R>(c, rolling, model, dt, (R)dn, n, vij, wrel, vr, me, (R)Ri, (R)Ri, dtl, Fi, Mi);
+  wall_law<R>(c, rolling, model, dt, W, g.n, g.dn, g.arm, xi, vi, wi, dtl, Fi, Mi);
 }
 
 // ------------------------------------------------------------------- force
@@ -876,7 +1021,8 @@ __device__ __forceinline__ double force_particle(
     const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
     const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
     double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
-    const int* __restrict__ flags, const bool want_drift, const TileT& tile) {
+    const int* __restrict__ flags, const bool want_drift, const double4* __restrict__ Fx,
+    const double4* __restrict__ Tx, const TileT& tile) {
   const int n = sp.n;
   double4 xi = tile.pos(in, i);
   double4 vi = tile.vel(in, i);
@@ -969,6 +1115,15 @@ __device__ __forceinline__ double force_particle(
     T[1] += Mi[1];
     T[2] += Mi[2];
   }
+  if (Fx) {
+    const double4 fx = Fx[i], tx = Tx[i];
+    F[0] += fx.x;
+    F[1] += fx.y;
+    F[2] += fx.z;
+    T[0] += tx.x;
+    T[1] += tx.y;
+    T[2] += tx.z;
+  }
   // integration of particle i (vel.w = 1/m, omg.w = 1/I)
   const double im = vi.w, iI = wi.w;
   const double a[3] = {F[0] * im + sp.g[0], F[1] * im + sp.g[1], F[2] * im + sp.g[2]};
@@ -1040,7 +1195,8 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
         const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
         ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
         double4* __restrict__ Fo, double4* __restrict__ To, const int64_t* __restrict__ clock,
-        int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift) {
+        int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift,
+        const double4* __restrict__ Fx, const double4* __restrict__ Tx) {
   const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
   __shared__ Tile<BS> tile;
@@ -1049,7 +1205,8 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   double d = 0.0;
   if (i < sp.n)
     d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
-                                       To, clock, step_rel, flags, drift != nullptr, tile);
+                                       To, clock, step_rel, flags, drift != nullptr, Fx, Tx,
+                                       tile);
   if (drift) wave_max_to(drift, d, BS / 64);
 }
 
@@ -1058,8 +1215,8 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, int block,
-                        hipStream_t s) {
+                        const int* flags, unsigned long long* drift, const double4* Fx,
+                        const double4* Tx, int block, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   dim3 gr(grid_for(sp.n, block)), bl(block);
@@ -1067,13 +1224,13 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
   do {                                                                                        \
     if (block == 64)                                                                          \
       hipLaunchKernelGGL((k_force<RT, M, L, 64>), gr, bl, 0, s, sp, inst, pp, pw, walls, in,  \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
     else if (block == 128)                                                                    \
       hipLaunchKernelGGL((k_force<RT, M, L, 128>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
     else                                                                                      \
       hipLaunchKernelGGL((k_force<RT, M, L, 256>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
   } while (0)
 #define DEM_LAUNCH_MODE(RT, L)                \
   do {                                        \
@@ -1090,6 +1247,148 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
   }
 #undef DEM_LAUNCH_MODE
 #undef DEM_LAUNCH
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ mesh contacts
+//
+// One thread per particle over its triangle candidates (at most kMeshSlots).
+// Every candidate reports its closest point and feature.  A face touches
+// when the centre is less than R above its plane.  The distance restricted
+// to one triangle is convex, so a point on an edge or at a vertex is a local
+// minimum of the distance over the surface exactly when every triangle
+// around it has it as its closest point: an edge or vertex counts when every
+// candidate triangle of the same mesh that contains it reports it, once, in
+// the slot of the first candidate reporting it, and touches when closer
+// than R.  Slots without a contact restart their tangential overlap at zero.
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock)
+k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls,
+       MeshTables mt, ParticleBufs in, const int* __restrict__ info, MeshSlots ms,
+       double4* __restrict__ Fm, double4* __restrict__ Tm, const int64_t* __restrict__ clock,
+       int64_t step_rel, const int* __restrict__ flags) {
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  const int n = sp.n;
+  if (i >= n) return;
+  double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+  const int inf = info[i];
+  if (ms.tri[i] >= 0 && !(inf & kInactive) && *flags == 0) {
+    const double4 xi = in.pos[i], vi = in.vel[i], wi = in.omg[i];
+    const double x[3] = {xi.x, xi.y, xi.z};
+    const double rad = xi.w;
+    const double t = (double)(*clock + step_rel) * sp.dt;
+    const int row = ((inf >> kInstShift) * kMaxTypes + (inf & kTypeMask)) * kMaxTypes;
+    // features reported by the candidates
+    int tri[kMeshSlots], wl[kMeshSlots], kind[kMeshSlots], fa[kMeshSlots], fb[kMeshSlots];
+    int tv[kMeshSlots][3];
+    double sd[kMeshSlots], d2[kMeshSlots];
+#pragma unroll
+    for (int k = 0; k < kMeshSlots; ++k) {
+      const int tr = ms.tri[(int64_t)k * n + i];
+      tri[k] = tr;
+      wl[k] = -1;
+      kind[k] = fa[k] = fb[k] = -1;
+      tv[k][0] = tv[k][1] = tv[k][2] = -1;
+      sd[k] = d2[k] = 0.0;
+      if (tr < 0) continue;
+      const TriDev& Tt = mt.tri[tr];
+      TriGeo g;
+      tri_closest(Tt, walls[Tt.wall].vel, t, x, g);
+      wl[k] = Tt.wall;
+      tv[k][0] = Tt.v[0];
+      tv[k][1] = Tt.v[1];
+      tv[k][2] = Tt.v[2];
+      kind[k] = g.feature;
+      sd[k] = g.s;
+      d2[k] = g.d2;
+      if (g.feature == 0) {
+        fa[k] = tr;
+      } else if (g.feature == 1) {
+        const int va = Tt.v[g.a], vb = Tt.v[g.b];
+        fa[k] = va < vb ? va : vb;
+        fb[k] = va < vb ? vb : va;
+      } else {
+        fa[k] = Tt.v[g.a];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMeshSlots; ++k) {
+      if (tri[k] < 0) continue;
+      const WallDev& W = walls[wl[k]];
+      bool contact = false;
+      if (t >= W.t_on && t < W.t_off) {
+        if (kind[k] == 0) {
+          contact = sd[k] < rad;
+        } else {
+          bool dropped = false, owner = true;
+#pragma unroll
+          for (int j = 0; j < kMeshSlots; ++j) {
+            if (tri[j] < 0 || wl[j] != wl[k]) continue;
+            const bool same = kind[j] == kind[k] && fa[j] == fa[k] && fb[j] == fb[k];
+            const bool has_a = tv[j][0] == fa[k] || tv[j][1] == fa[k] || tv[j][2] == fa[k];
+            const bool has_b = tv[j][0] == fb[k] || tv[j][1] == fb[k] || tv[j][2] == fb[k];
+            if (has_a && (kind[k] == 2 || has_b) && !same) dropped = true;
+            if (j < k && same) owner = false;
+          }
+          contact = !dropped && owner && d2[k] < rad * rad && d2[k] > 0.0;
+        }
+      }
+      const int64_t h = (int64_t)(3 * k) * n + i;
+      if (!contact) {
+        ms.hist[h] = 0.0;
+        ms.hist[h + n] = 0.0;
+        ms.hist[h + 2 * (int64_t)n] = 0.0;
+        continue;
+      }
+      TriGeo g;
+      tri_closest(mt.tri[tri[k]], W.vel, t, x, g);
+      double gn[3], gdn;
+      if (kind[k] == 0) {
+        const double* tn = mt.tri[tri[k]].n;
+        gn[0] = -tn[0];
+        gn[1] = -tn[1];
+        gn[2] = -tn[2];
+        gdn = rad - sd[k];
+      } else {
+        const double dist = sqrt(d2[k]);
+        gn[0] = (g.q[0] - x[0]) / dist;
+        gn[1] = (g.q[1] - x[1]) / dist;
+        gn[2] = (g.q[2] - x[2]) / dist;
+        gdn = rad - dist;
+      }
+      const double arm[3] = {g.q[0] - (W.ax[0] + W.vel[0] * t), g.q[1] - (W.ax[1] + W.vel[1] * t),
+                             g.q[2] - (W.ax[2] + W.vel[2] * t)};
+      double dtl[3] = {ms.hist[h], ms.hist[h + n], ms.hist[h + 2 * (int64_t)n]};
+      double Fi[3], Mi[3];
+      wall_law<R>(pwc[row + W.material], sp.rolling, sp.model, sp.dt, W, gn, gdn, arm, xi, vi, wi,
+                  dtl, Fi, Mi);
+      ms.hist[h] = dtl[0];
+      ms.hist[h + n] = dtl[1];
+      ms.hist[h + 2 * (int64_t)n] = dtl[2];
+      F[0] += Fi[0];
+      F[1] += Fi[1];
+      F[2] += Fi[2];
+      T[0] += Mi[0];
+      T[1] += Mi[1];
+      T[2] += Mi[2];
+    }
+  }
+  Fm[i] = make_double4(F[0], F[1], F[2], 0.0);
+  Tm[i] = make_double4(T[0], T[1], T[2], 0.0);
+}
+
+hipError_t launch_mesh(int precision, const StepParams& sp, const PairCoef* pw,
+                       const WallDev* walls, MeshTables mt, ParticleBufs in, const int* info,
+                       MeshSlots ms, double4* Fm, double4* Tm, const int64_t* clock,
+                       int64_t step_rel, const int* flags, hipStream_t s) {
+  if (sp.n <= 0) return hipSuccess;
+  if (precision == 0)
+    hipLaunchKernelGGL(k_mesh<double>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, pw, walls,
+                       mt, in, info, ms, Fm, Tm, clock, step_rel, flags);
+  else
+    hipLaunchKernelGGL(k_mesh<float>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, pw, walls,
+                       mt, in, info, ms, Fm, Tm, clock, step_rel, flags);
   return hipGetLastError();
 }
 

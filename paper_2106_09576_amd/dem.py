@@ -102,6 +102,9 @@ SIGNATURES = {
     "dem_get_forces": (C.c_int, [P, C.c_int32, DP, DP]),
     "dem_get_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, U8P, I64P]),
     "dem_get_wall_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
+    "dem_add_mesh_wall": (C.c_int, [P, C.c_int32, C.c_int64, DP, C.c_int64, I32P, C.c_int32, DP,
+                                    DP, C.c_double, C.c_double, I32P]),
+    "dem_get_mesh_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_resort": (C.c_int, [P]),
     "dem_get_stats": (C.c_int, [P, C.POINTER(dem_stats)]),
     "dem_stream": (C.c_void_p, [P]),
@@ -229,6 +232,19 @@ class Dem:
                                                 t_on, t_off, C.byref(wid)))
         return wid.value
 
+    def add_mesh_wall(self, vertices, triangles, material=0, axis_point=None, omega=None,
+                      t_on=-np.inf, t_off=np.inf, instance=0):
+        """Triangle-mesh wall; each triangle's corners ordered so that
+        (p1 - p0) x (p2 - p0) points to the particles' side."""
+        V = np.ascontiguousarray(vertices, dtype=np.float64).reshape(-1, 3)
+        T = np.ascontiguousarray(triangles, dtype=np.int32).reshape(-1, 3)
+        wid = C.c_int32()
+        ap, om = _v3(axis_point), _v3(omega)
+        self._check(self._lib.dem_add_mesh_wall(self._h, instance, V.shape[0], _d(V), T.shape[0],
+                                                T.ctypes.data_as(I32P), material, _d(ap),
+                                                _d(om), t_on, t_off, C.byref(wid)))
+        return wid.value
+
     def set_wall_motion(self, wall_id, velocity, instance=0):
         """Translate wall ``wall_id`` at constant ``velocity`` (before set_particles)."""
         v = _v3(velocity)
@@ -303,6 +319,21 @@ class Dem:
                                                     pairs.ctypes.data_as(I64P), _d(dt),
                                                     C.byref(cnt)))
         return pairs[:m], dt[:m]
+
+    def get_mesh_contacts(self, instance=0):
+        """(particle, wall, triangle) candidates of mesh walls and their
+        tangential overlaps, sorted."""
+        cnt = C.c_int64()
+        rc = self._lib.dem_get_mesh_contacts(self._h, instance, 0, None, None, C.byref(cnt))
+        if rc not in (DEM_OK, DEM_EINVAL):
+            self._check(rc)
+        m = cnt.value
+        tr = np.empty((max(m, 1), 3), dtype=np.int64)
+        dt = np.empty((max(m, 1), 3))
+        self._check(self._lib.dem_get_mesh_contacts(self._h, instance, max(m, 1),
+                                                    tr.ctypes.data_as(I64P), _d(dt),
+                                                    C.byref(cnt)))
+        return tr[:m], dt[:m]
 
     def resort(self):
         self._check(self._lib.dem_resort(self._h))
@@ -379,6 +410,10 @@ class Dem:
                 wid = self.add_planar_wall(w["point"], w["normal"], w["material"],
                                            w.get("extent"), w.get("axis_point"), w.get("omega"),
                                            w["t_on"], w["t_off"], instance=instance)
+            elif w["kind"] == "mesh":
+                wid = self.add_mesh_wall(w["vertices"], w["triangles"], w["material"],
+                                         w.get("axis_point"), w.get("omega"), w["t_on"],
+                                         w["t_off"], instance=instance)
             elif w["kind"] == "cylinder":
                 wid = self.add_cylinder_wall(w["axis_point"], w["axis_dir"], w["radius"],
                                              w["s_min"], w["s_max"], w["inside"], w["material"],

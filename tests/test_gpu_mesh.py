@@ -1,0 +1,201 @@
+"""GPU parity with mesh walls (Sec. 3.7: particle-face, particle-line and
+particle-point contacts), through the C ABI against the oracle.
+
+Scenes: a dense snapshot inside a triangulated box (concave edges and
+corners); the 3,000-sphere hopper silo with its cone replaced by a spinning
+triangulated frustum (faces, and the convex rim of the outlet); spheres
+thrown onto a roof and a pyramid (convex ridge, edges and apex); a
+translating triangulated plate.  Particle-triangle candidate triples are
+compared bit for bit, forces within the law's tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle_from_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Dem():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_09576_amd import Dem as D
+    return D
+
+
+def sets_equal(g, o):
+    gp, gd, gt = g.get_contacts()
+    op, od, ot = o.contacts()
+    assert np.array_equal(gp, op) and np.array_equal(gt, ot)
+    gw, _ = g.get_wall_contacts()
+    ow, _ = o.wall_contacts()
+    assert np.array_equal(gw, ow)
+    gm, _ = g.get_mesh_contacts()
+    om, _ = o.mesh_contacts()
+    assert np.array_equal(gm, om)
+    return int(gt.sum()), len(gm)
+
+
+def force_err(g, o, radius):
+    Fg, Tg = g.get_forces()
+    Fo, To, S = o.forces()
+    ef = np.max(np.linalg.norm(Fg - Fo, axis=1) / (np.linalg.norm(Fo, axis=1) + S + 1e-300))
+    et = np.max(np.linalg.norm(Tg - To, axis=1) /
+                (np.linalg.norm(To, axis=1) + S * radius + 1e-300))
+    return ef, et
+
+
+def meshed_box():
+    sc = W.dense_snapshot(n=2500, seed=31, polydisperse=0.1, n_types=2, K=10)
+    n = [np.array(w["normal"]) for w in sc["walls"]]
+    lo = [w["point"] for w, nn in zip(sc["walls"], n) if nn.sum() > 0][0]
+    hi = [w["point"] for w, nn in zip(sc["walls"], n) if nn.sum() < 0][0]
+    return dict(sc, walls=[W.box_mesh(lo, hi, divisions=4)])
+
+
+def meshed_hopper():
+    # spheres start slightly into the cone, so that its faces act at once
+    sc = W.hopper_silo_scene(n=3000, spacing=0.8, clearance=0.7, t_open=300 * 2e-6, K=10)
+    rng = np.random.default_rng(17)
+    sc["particles"]["omega"] = rng.uniform(-20.0, 20.0, sc["particles"]["pos"].shape)
+    cone = sc["walls"][0]
+    frustum = W.frustum_mesh(cone["axis_point"], cone["radius0"], cone["slope"], cone["s_min"],
+                             cone["s_max"], segments=48, rings=20, omega=1.5)
+    return dict(sc, walls=[frustum] + sc["walls"][1:])
+
+
+def roof_and_pyramid(n_side=24, seed=5):
+    """A roof (ridge along y) and a pyramid side by side on a floor, spheres
+    raining onto them from a lattice just above, with random velocities and
+    spins."""
+    rng = np.random.default_rng(seed)
+    R = 1.5e-3
+    a = math.radians(30.0)
+    L = 0.04
+    dx, dz = L * math.cos(a), -L * math.sin(a)
+    V1 = np.array([(0, -L, 0), (0, L, 0), (-dx, -L, dz), (-dx, L, dz), (dx, -L, dz), (dx, L, dz)])
+    T1 = np.array([(0, 1, 3), (0, 3, 2), (0, 5, 1), (0, 4, 5)])
+    c = np.array([0.1, 0.0, 0.0])
+    V2 = np.array([(0, 0, 0), (-L, -L, -0.02), (L, -L, -0.02), (L, L, -0.02), (-L, L, -0.02)]) + c
+    T2 = np.array([(0, 1, 2), (0, 2, 3), (0, 3, 4), (0, 4, 1)])
+    xs = np.linspace(-0.03, 0.13, n_side)
+    ys = np.linspace(-0.03, 0.03, n_side // 2)
+    pts = []
+    for x in xs:
+        for y in ys:
+            # height of the surface below (roof or pyramid), then just above it
+            zr = -abs(x) * math.tan(a) if abs(x) < dx else -0.03
+            zp = (-max(abs(x - c[0]), abs(y)) * 0.02 / L) if max(abs(x - c[0]), abs(y)) < L else -0.03
+            z = max(zr, zp, -0.03)
+            pts.append((x, y, z + R * 1.2 + 2e-4 * rng.random()))
+    pts = np.array(pts)
+    vel = np.column_stack([rng.normal(0, 0.05, len(pts)), rng.normal(0, 0.05, len(pts)),
+                           -0.3 - 0.1 * rng.random(len(pts))])
+    om = rng.uniform(-30, 30, (len(pts), 3))
+    cfg = W._cfg(1e-5, (-0.06, -0.06, -0.06), (0.16, 0.06, 0.06), K=10)
+    walls = [W.mesh(V1, T1), W.mesh(V2, T2), W.plane((0, 0, -0.03), (0, 0, 1))]
+    return dict(name="roof_pyramid", config=cfg, materials=[dict(W.BOX_MATERIAL)], walls=walls,
+                particles=W._particles(pts, R, vel, om))
+
+
+SCENES = {"box": meshed_box, "hopper": meshed_hopper, "roof": roof_and_pyramid}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mesh_walls_parity(Dem, name, precision):
+    sc = SCENES[name]()
+    R = sc["particles"]["radius"]
+    g = Dem.from_scene(sc, precision=precision)
+    o = oracle_from_scene(sc)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    g.step(1)
+    o.step(1)
+    nt, nm = sets_equal(g, o)
+    ef, et = force_err(g, o, R)
+    print(name, precision, "step 1: touching", nt, "triangle candidates", nm, "err", ef, et,
+          flush=True)
+    assert nm > 20 and ef <= tol and et <= tol
+    # FP32: 20 steps (later on, the constant rolling torque of spheres coming
+    # to rest takes the direction of a relative spin at the rounding level)
+    for chunk in ((19, 30) if precision == "fp64" else (19,)):
+        g.step(chunk)
+        o.step(chunk)
+        nt, nm = sets_equal(g, o)
+        ef, et = force_err(g, o, R)
+        dx = np.max(np.abs(g.get_state()["pos"] - o.state()["pos"]))
+        print(name, precision, "step", g.get_stats()["step"], "err", ef, et, "dx", dx,
+              "triangle candidates", nm, flush=True)
+        assert ef <= max(10 * tol, 1e-9) and et <= max(10 * tol, 1e-9)
+        assert dx <= (1e-12 if precision == "fp64" else 1e-9)
+    # tangential overlaps kept in the candidates' slots
+    _, dto = o.mesh_contacts()
+    _, dtg = g.get_mesh_contacts()
+    assert np.max(np.abs(dtg - dto)) <= (1e-9 if precision == "fp64" else 1e-3) * \
+        (np.max(np.abs(dto)) + 1e-300)
+    if precision == "fp64":
+        assert np.count_nonzero(np.any(dto != 0, axis=1)) >= 5  # at step 50
+        for chunk in (100, 150):
+            g.step(chunk)
+            o.step(chunk)
+            sets_equal(g, o)
+
+
+def test_translating_mesh_plate(Dem):
+    """A triangulated plate moving at 0.3 m/s sweeps spheres at rest."""
+    rng = np.random.default_rng(2)
+    R = 1.5e-3
+    pts = W.rsa_box(200, R, (0.005, -0.02, -0.02), (0.03, 0.02, 0.02), rng)
+    Vx = np.array([(0, -0.03, -0.03), (0, 0.03, -0.03), (0, 0.03, 0.03), (0, -0.03, 0.03)])
+    plate = W.mesh(Vx, np.array([(0, 1, 2), (0, 2, 3)]), velocity=(0.3, 0.0, 0.0))
+    cfg = W._cfg(1e-5, (-0.01, -0.05, -0.05), (0.1, 0.05, 0.05), K=10, gravity=(0, 0, 0))
+    sc = dict(name="plate", config=cfg, materials=[dict(W.BOX_MATERIAL)], walls=[plate],
+              particles=W._particles(pts, R))
+    g, o = Dem.from_scene(sc), oracle_from_scene(sc)
+    for chunk in (1000, 1000):
+        g.step(chunk)
+        o.step(chunk)
+        nt, nm = sets_equal(g, o)
+        print("plate", g.get_state()["time"], "touching", nt, "triangle candidates", nm,
+              flush=True)
+    assert nm > 10
+    assert np.max(np.abs(g.get_state()["pos"] - o.state()["pos"])) <= 1e-9
+    assert np.max(g.get_state()["vel"][:, 0]) > 0.3
+
+
+def test_too_many_triangle_candidates_is_reported(Dem):
+    """A fine mesh (triangles much smaller than the sphere) overflows the 8
+    candidate slots: a capacity error, not a silent miss."""
+    m = 40
+    xs = np.linspace(-0.01, 0.01, m + 1)
+    V = np.array([(x, y, 0.0) for y in xs for x in xs])
+    T = []
+    for j in range(m):
+        for i in range(m):
+            a, b = j * (m + 1) + i, j * (m + 1) + i + 1
+            T += [(a, b, b + m + 1), (a, b + m + 1, a + m + 1)]
+    cfg = W._cfg(1e-5, (-0.05,) * 3, (0.05,) * 3, K=10)
+    sc = dict(name="fine", config=cfg, materials=[dict(W.BOX_MATERIAL)],
+              walls=[W.mesh(V, np.array(T))], particles=W._particles([[0.0, 0.0, 1.6e-3]], 1.5e-3))
+    with pytest.raises(Exception, match="capacity"):
+        g = Dem.from_scene(sc)
+        g.step(1)
+
+
+def test_mesh_wall_argument_checks(Dem):
+    sim = Dem(dt=1e-5)
+    sim.set_material(0, 2500.0, 1e6, 0.3, 0.9, 0.3, 0.1)
+    with pytest.raises(Exception):
+        sim.add_mesh_wall([[0, 0, 0], [1, 0, 0], [2, 0, 0]], [[0, 1, 2]])  # degenerate
+    with pytest.raises(Exception):
+        sim.add_mesh_wall([[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 3]])  # bad index
+    sim.add_mesh_wall([[0, 0, 0], [1, 0, 0], [0, 1, 0]], [[0, 1, 2]])
+    sim.set_particles([[0.2, 0.2, 0.01]], [1e-3])
+    ck = sim.checkpoint()
+    with pytest.raises(Exception, match="mesh"):
+        sim.restore(ck)
