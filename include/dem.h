@@ -193,8 +193,7 @@ int dem_add_cone_wall(dem_ctx* ctx, int32_t instance, const double axis_point[3]
    active for t_on <= t < t_off.  At most 2^24 triangles per instance;
    DEM_EINVAL for out-of-range corner indices, degenerate triangles or
    non-finite corners.  The arrays are copied.  Walls are added before
-   dem_set_particles (else DEM_ESTATE).  dem_restore does not support
-   contexts with mesh walls. */
+   dem_set_particles (else DEM_ESTATE). */
 int dem_add_mesh_wall(dem_ctx* ctx, int32_t instance, int64_t n_vertices,
                       const double* vertices, int64_t n_triangles, const int32_t* triangles,
                       int32_t material, const double axis_point[3], const double omega[3],
@@ -281,11 +280,23 @@ int dem_get_state_device(dem_ctx* ctx, int32_t instance, double* pos, double* ve
    the constant schedule), which is also when the resumed run repeats the
    saved one bit for bit.  Histories of the instance not listed are zeroed.
    Host arrays are read and copied; DEM_EINVAL for a pair or wall contact that
-   is not in the lists (nothing is changed on the device then). */
+   is not in the lists (nothing is changed on the device then, except, with
+   translating walls, the step count and the contact search at the restored
+   time that precede the check). */
 int dem_restore(dem_ctx* ctx, int32_t instance, int64_t n_pairs, const int64_t* pairs,
                 const double* delta_t, int64_t n_wall, const int64_t* wall_pairs,
                 const double* wall_delta_t, const double* force, const double* torque,
                 int64_t step);
+
+/* Exact resume, mesh walls: after dem_restore, the tangential overlaps of
+   n_tri particle-triangle candidates given as (gid, wall id, triangle index
+   within the wall) triples (n_tri x 3) with their overlaps (n_tri x 3), as
+   dem_get_mesh_contacts returned them in the saved context; the overlaps of
+   the instance's other triangle candidates are zeroed.  DEM_EINVAL for a
+   triple that is not a candidate of the current lists (nothing is changed
+   on the device then). */
+int dem_restore_mesh_contacts(dem_ctx* ctx, int32_t instance, int64_t n_tri,
+                              const int64_t* triples, const double* delta_t);
 
 /* Total contact force and torque on every particle from the last force
    evaluation of the last dem_step call (zero before the first step). */

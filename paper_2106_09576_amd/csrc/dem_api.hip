@@ -1835,19 +1835,18 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
   if (int rc = check_instance(c, instance)) return rc;
   if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
   if (n_pairs < 0 || n_wall < 0) return set_err(DEM_EINVAL, "negative count");
-  if (c->has_mesh)
-    return set_err(DEM_EINVAL, "restoring contacts with mesh walls is not supported");
   if ((n_pairs > 0 && (!pairs || !delta_t)) || (n_wall > 0 && (!wall_pairs || !wall_delta_t)))
     return set_err(DEM_EINVAL, "null array");
   if (int rc = wait_user(c)) return rc;
-  if (step >= 0) {
+  const bool moving = c->n > 0 && wall_rate(c) > 0.0;
+  if (step >= 0 && moving) {
     c->step = step;
     c->host_base = step;
     HIPCHK(hipMemcpyAsync(c->d_clock, &c->host_base, sizeof(int64_t), hipMemcpyHostToDevice,
                           c->stream));
     // translating walls: search again with the walls where they are at the
     // restored time (the lists were built with them elsewhere)
-    if (c->n > 0 && wall_rate(c) > 0.0) {
+    {
       if (int rc = enqueue_rebuild(c, 0, 1, 0)) return rc;
       c->dyn_acc = 0.0;
       c->dyn_wacc = 0.0;
@@ -1951,6 +1950,68 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
     HIPCHK(hipMemcpyAsync(c->T[L], T.data(), n * sizeof(double4), hipMemcpyHostToDevice,
                           c->stream));
   }
+  if (step >= 0 && !moving) {
+    c->step = step;
+    c->host_base = step;
+    HIPCHK(hipMemcpyAsync(c->d_clock, &c->host_base, sizeof(int64_t), hipMemcpyHostToDevice,
+                          c->stream));
+  }
+  return finish(c);
+}
+
+int dem_restore_mesh_contacts(dem_ctx* c, int32_t instance, int64_t n_tri,
+                              const int64_t* triples, const double* delta_t) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
+  if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
+  if (n_tri < 0) return set_err(DEM_EINVAL, "negative count");
+  if (n_tri > 0 && (!triples || !delta_t)) return set_err(DEM_EINVAL, "null array");
+  if (!c->has_mesh) {
+    if (n_tri > 0) return set_err(DEM_EINVAL, "no mesh walls");
+    return DEM_OK;
+  }
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  const int L = c->pcur;
+  const Instance& In = c->inst[(size_t)instance];
+  std::vector<int> where((size_t)In.n, -1);
+  for (size_t p = 0; p < n; ++p)
+    if ((h.info[p] >> kInstShift) == instance) where[(size_t)(h.gid[p] - In.p_begin)] = (int)p;
+  std::vector<int> tr(n * kMeshSlots);
+  std::vector<double> th(n * kMeshSlots * 3);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(tr.data(), c->mtri[L], tr.size() * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(th.data(), c->mhist[L], th.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    for (int a = 0; a < 3 * kMeshSlots; ++a) th[(size_t)a * n + p] = 0.0;
+  }
+  for (int64_t m = 0; m < n_tri; ++m) {
+    const int64_t g = triples[3 * m], wl = triples[3 * m + 1], tl = triples[3 * m + 2];
+    const int p = g >= 0 && g < In.n ? where[(size_t)g] : -1;
+    if (p < 0 || wl < 0 || wl >= (int64_t)In.walls.size() || In.walls[(size_t)wl].kind != 3 ||
+        tl < 0 || tl >= In.walls[(size_t)wl].tri_count)
+      return set_err(DEM_EINVAL, "mesh contact %lld out of range", (long long)m);
+    const int gt = In.walls[(size_t)wl].tri_begin + (int)tl;
+    bool found = false;
+    for (int sl = 0; sl < kMeshSlots && !found; ++sl) {
+      if (tr[(size_t)sl * n + (size_t)p] != gt) continue;
+      for (int a = 0; a < 3; ++a) th[(size_t)(3 * sl + a) * n + (size_t)p] = delta_t[3 * m + a];
+      found = true;
+    }
+    if (!found)
+      return set_err(DEM_EINVAL, "particle %lld is not a candidate of triangle %lld of wall %lld",
+                     (long long)g, (long long)tl, (long long)wl);
+  }
+  if (n > 0)
+    HIPCHK(hipMemcpyAsync(c->mhist[L], th.data(), th.size() * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
   return finish(c);
 }
 

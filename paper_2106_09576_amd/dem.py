@@ -105,6 +105,7 @@ SIGNATURES = {
     "dem_add_mesh_wall": (C.c_int, [P, C.c_int32, C.c_int64, DP, C.c_int64, I32P, C.c_int32, DP,
                                     DP, C.c_double, C.c_double, I32P]),
     "dem_get_mesh_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
+    "dem_restore_mesh_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP]),
     "dem_resort": (C.c_int, [P]),
     "dem_get_stats": (C.c_int, [P, C.POINTER(dem_stats)]),
     "dem_stream": (C.c_void_p, [P]),
@@ -351,12 +352,14 @@ class Dem:
         st = self.get_state(instance)
         pairs, dt, touching = self.get_contacts(instance)
         wpairs, wdt = self.get_wall_contacts(instance)
+        mtri, mdt = self.get_mesh_contacts(instance)
         F, T = self.get_forces(instance)
         t = touching.astype(bool)
+        keep = np.any(mdt != 0, axis=1)
         return {"pos": st["pos"], "vel": st["vel"], "omega": st["omega"],
                 "pairs": pairs[t], "delta_t": dt[t], "wall_pairs": wpairs,
-                "wall_delta_t": wdt, "force": F, "torque": T,
-                "step": self.get_stats()["step"]}
+                "wall_delta_t": wdt, "mesh_triples": mtri[keep], "mesh_delta_t": mdt[keep],
+                "force": F, "torque": T, "step": self.get_stats()["step"]}
 
     def restore(self, ck, instance=0):
         """Restore histories, forces and step count of a checkpoint into an
@@ -371,6 +374,13 @@ class Dem:
                                           pairs.ctypes.data_as(I64P), _d(dt), wp.shape[0],
                                           wp.ctypes.data_as(I64P), _d(wdt), _d(F), _d(T),
                                           int(ck["step"])))
+        mt = np.ascontiguousarray(ck.get("mesh_triples", np.zeros((0, 3))),
+                                  dtype=np.int64).reshape(-1, 3)
+        mdt = np.ascontiguousarray(ck.get("mesh_delta_t", np.zeros((0, 3))),
+                                   dtype=np.float64).reshape(-1, 3)
+        if mt.shape[0]:
+            self._check(self._lib.dem_restore_mesh_contacts(self._h, instance, mt.shape[0],
+                                                            mt.ctypes.data_as(I64P), _d(mdt)))
 
     def autotune(self, trial_steps=200):
         """Tune force block size, cell edge and search schedule on the running
