@@ -13,8 +13,9 @@ One step = contact search when due (the "dynamic" schedule: when a particle
 may have moved half the skin) + particle-particle and particle-wall
 Hertz-Mindlin forces with tangential history + velocity-Verlet integration,
 all in the library's HIP kernels.  Also timed: the same drum with a search
-every 20 steps, with live autotuning, the batch of 256 drums, the dam break
-of 1.28M spheres and the 1,000-sphere box.  Prints one JSON line.
+every 20 steps, with live autotuning, with the linear law and with viscous
+rolling, with a triangulated cylinder, the batch of 256 drums, the dam
+break of 1.28M spheres and the 1,000-sphere box.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -247,6 +248,34 @@ def measure_dam_break(args, precs):
             "results": res}
 
 
+def measure_variants(args, base_scene):
+    """The drum with the other contact laws of Sec. 2.1 (FP64 law): the linear
+    spring-dashpot model (characteristic velocity 0.5 m/s) and the viscous
+    rolling torque, same settling and timing as the headline legs."""
+    out = {}
+    for label, cfg in (("linear", dict(contact_model="linear", characteristic_velocity=0.5)),
+                       ("viscous_rolling", dict(rolling_model="viscous"))):
+        sc = dict(base_scene, config=dict(base_scene["config"], rebuild_interval=0, **cfg))
+        out[label] = measure(args, "fp64", sc, label=f"fp64 {label}",
+                             force_block=MAIN_FORCE_BLOCK)
+    return {"workload": "the headline drum with the linear spring-dashpot law (V = 0.5 m/s) "
+                        "and with the viscous rolling torque, FP64 law", "results": out}
+
+
+def measure_meshed_drum(args):
+    """The headline drum with its cylinder as a spinning triangle mesh of
+    192 x 48 squares (18,432 triangles): particle-face/edge/vertex contacts
+    in their own kernel each step (its time is inside the force time
+    reported here)."""
+    import workloads as W
+    sc = W.meshed_drum_scene(n=args.n, segments=192, rings=48)
+    sc = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+    res = measure(args, "fp64", sc, label="fp64 meshed drum", force_block=MAIN_FORCE_BLOCK)
+    return {"workload": (f"rotating drum of {args.n} spheres as the headline, its cylinder a "
+                         f"spinning mesh of 18,432 triangles; force time includes the mesh "
+                         f"contact kernel"), "results": {"fp64": res}}
+
+
 def copy_bandwidth():
     """Achievable device bandwidth: five copies of 1 GiB (read 1 GiB, write
     1 GiB each) timed with HIP events, after one untimed copy."""
@@ -307,6 +336,9 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=200,
                     help="steps per autotuner trial")
     ap.add_argument("--skip-dam", action="store_true", help="skip the dam-break legs")
+    ap.add_argument("--skip-variants", action="store_true",
+                    help="skip the drum legs with the linear law and viscous rolling")
+    ap.add_argument("--skip-mesh", action="store_true", help="skip the meshed-drum leg")
     ap.add_argument("--dam-n", type=int, default=1_280_000)
     ap.add_argument("--dam-steps", type=int, default=4000,
                     help="steps with the dam standing, then timed steps after its removal")
@@ -415,6 +447,10 @@ def main():
         }
         if "fp32" in b and "fp64" in b:
             out["batched"]["fp32_vs_fp64"] = b["fp32"]["value"] / b["fp64"]["value"]
+    if not args.skip_variants:
+        out["model_variants"] = measure_variants(args, scene)
+    if not args.skip_mesh:
+        out["meshed_drum"] = measure_meshed_drum(args)
     if not args.skip_dam:
         out["dam_break"] = measure_dam_break(args, precs)
     if not args.skip_small:

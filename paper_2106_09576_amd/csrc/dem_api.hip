@@ -341,8 +341,8 @@ int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* dr
   HIPCHK(launch_force(mode, c->cfg.precision, c->sp, c->d_inst, c->d_pp, c->d_pw, c->d_walls,
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
-                      c->d_clock, step_rel, c->d_flags, drift, c->Fm, c->Tm, c->force_block,
-                      c->stream));
+                      c->d_clock, step_rel, c->d_flags, drift, c->has_mesh ? c->mtri[p] : nullptr,
+                      c->Fm, c->Tm, c->force_block, c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }

@@ -197,18 +197,19 @@ hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double
 // kick of this step, first half kick and drift of the next), 1 = velocity
 // Verlet last step of a call (second half kick, forces stored), 2 = explicit
 // Euler (forces at the current state, then the update; forces stored).
-// Fx / Tx (may be null): further force and torque per particle, added to the
-// contact sums (the mesh contacts of the same state).
+// xsel (may be null): particles i with xsel[i] >= 0 add the force and torque
+// Fx[i] / Tx[i] to their contact sums (the mesh contacts of the same state;
+// xsel is the first mesh candidate slot).
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
                         const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, const double4* Fx,
-                        const double4* Tx, int block, hipStream_t s);
-// Contacts of every particle with mesh walls at time (*clock + step_rel) dt,
-// from its triangle candidates (tangential overlaps updated): force and
-// torque per particle into Fm / Tm (zero without contacts).
+                        const int* flags, unsigned long long* drift, const int* xsel,
+                        const double4* Fx, const double4* Tx, int block, hipStream_t s);
+// Contacts of the particles with triangle candidates at time (*clock +
+// step_rel) dt (tangential overlaps updated): their force and torque into
+// Fm / Tm (written for those particles only).
 hipError_t launch_mesh(int precision, const StepParams& sp, const PairCoef* pw,
                        const WallDev* walls, MeshTables mt, ParticleBufs in, const int* info,
                        MeshSlots ms, double4* Fm, double4* Tm, const int64_t* clock,

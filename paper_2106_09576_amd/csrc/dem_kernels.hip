@@ -729,7 +729,19 @@ struct Fast<double> {
   static __device__ __forceinline__ double sqrt(double x) {
     return x > 0.0 ? x * rsqrt(x) : 0.0;
   }
-  static __device__ __forceinline__ double root5(double x) { return ::pow(x, 0.2); }
+  // fifth root: a single-precision estimate 2^(log2(x) / 5) refined by two
+  // steps of Newton's iteration for y^5 = x, y <- (4 y + x / y^4) / 5 (the
+  // error squares at each step: about 1e-7, 1e-14, then FP64 rounding)
+  static __device__ __forceinline__ double root5(double x) {
+    if (!(x > 0.0)) return 0.0;
+    double y = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)x) * 0.2f);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const double y2 = y * y;
+      y = 0.8 * y + (0.2 * x) * rcp(y2 * y2);
+    }
+    return y;
+  }
 };
 
 template <>
@@ -1021,8 +1033,8 @@ __device__ __forceinline__ double force_particle(
     const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
     const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
     double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
-    const int* __restrict__ flags, const bool want_drift, const double4* __restrict__ Fx,
-    const double4* __restrict__ Tx, const TileT& tile) {
+    const int* __restrict__ flags, const bool want_drift, const int* __restrict__ xsel,
+    const double4* __restrict__ Fx, const double4* __restrict__ Tx, const TileT& tile) {
   const int n = sp.n;
   double4 xi = tile.pos(in, i);
   double4 vi = tile.vel(in, i);
@@ -1115,7 +1127,7 @@ __device__ __forceinline__ double force_particle(
     T[1] += Mi[1];
     T[2] += Mi[2];
   }
-  if (Fx) {
+  if (xsel && xsel[i] >= 0) {
     const double4 fx = Fx[i], tx = Tx[i];
     F[0] += fx.x;
     F[1] += fx.y;
@@ -1187,16 +1199,19 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v,
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
 }
 
-// Occupancy floor: the nonlinear law fits 128 VGPRs (four wavefronts per
-// SIMD) without spills; the linear law needs more and keeps three.
+// Occupancy floor: four wavefronts per SIMD (128 VGPRs, no spills), except
+// for the linear law with explicit Euler, which would spill there and keeps
+// three.
 template <typename R, int MODE, int MODEL, int BS>
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(MODEL == 0 ? 4 : 3)))
+__global__ void __launch_bounds__(BS)
+    __attribute__((amdgpu_waves_per_eu(MODE == 2 && MODEL == 1 ? 3 : 4)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
         const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs in,
         ParticleBufs out, const int* __restrict__ info, NbrList l, WallSlots ws,
         double4* __restrict__ Fo, double4* __restrict__ To, const int64_t* __restrict__ clock,
         int64_t step_rel, const int* __restrict__ flags, unsigned long long* __restrict__ drift,
-        const double4* __restrict__ Fx, const double4* __restrict__ Tx) {
+        const int* __restrict__ xsel, const double4* __restrict__ Fx,
+        const double4* __restrict__ Tx) {
   const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
   __shared__ Tile<BS> tile;
@@ -1205,8 +1220,8 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   double d = 0.0;
   if (i < sp.n)
     d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
-                                       To, clock, step_rel, flags, drift != nullptr, Fx, Tx,
-                                       tile);
+                                       To, clock, step_rel, flags, drift != nullptr, xsel, Fx,
+                                       Tx, tile);
   if (drift) wave_max_to(drift, d, BS / 64);
 }
 
@@ -1215,8 +1230,8 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
-                        const int* flags, unsigned long long* drift, const double4* Fx,
-                        const double4* Tx, int block, hipStream_t s) {
+                        const int* flags, unsigned long long* drift, const int* xsel,
+                        const double4* Fx, const double4* Tx, int block, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   dim3 gr(grid_for(sp.n, block)), bl(block);
@@ -1224,13 +1239,13 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
   do {                                                                                        \
     if (block == 64)                                                                          \
       hipLaunchKernelGGL((k_force<RT, M, L, 64>), gr, bl, 0, s, sp, inst, pp, pw, walls, in,  \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx);              \
     else if (block == 128)                                                                    \
       hipLaunchKernelGGL((k_force<RT, M, L, 128>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx);              \
     else                                                                                      \
       hipLaunchKernelGGL((k_force<RT, M, L, 256>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, Fx, Tx);              \
+                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx);              \
   } while (0)
 #define DEM_LAUNCH_MODE(RT, L)                \
   do {                                        \
@@ -1262,8 +1277,9 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
 // the slot of the first candidate reporting it, and touches when closer
 // than R.  Slots without a contact restart their tangential overlap at zero.
 
+// three wavefronts per SIMD fit without spills (168 VGPRs)
 template <typename R>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls,
        MeshTables mt, ParticleBufs in, const int* __restrict__ info, MeshSlots ms,
        double4* __restrict__ Fm, double4* __restrict__ Tm, const int64_t* __restrict__ clock,
@@ -1273,7 +1289,9 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
   if (i >= n) return;
   double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
   const int inf = info[i];
-  if (ms.tri[i] >= 0 && !(inf & kInactive) && *flags == 0) {
+  // only particles with candidates: the force kernel reads Fm / Tm for them
+  if (ms.tri[i] < 0) return;
+  if (!(inf & kInactive) && *flags == 0) {
     const double4 xi = in.pos[i], vi = in.vel[i], wi = in.omg[i];
     const double x[3] = {xi.x, xi.y, xi.z};
     const double rad = xi.w;
@@ -1282,7 +1300,7 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
     // features reported by the candidates
     int tri[kMeshSlots], wl[kMeshSlots], kind[kMeshSlots], fa[kMeshSlots], fb[kMeshSlots];
     int tv[kMeshSlots][3];
-    double sd[kMeshSlots], d2[kMeshSlots];
+    unsigned near = 0u;  // bit k: slot k's closest point is closer than R (faces: above the plane)
 #pragma unroll
     for (int k = 0; k < kMeshSlots; ++k) {
       const int tr = ms.tri[(int64_t)k * n + i];
@@ -1290,7 +1308,6 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
       wl[k] = -1;
       kind[k] = fa[k] = fb[k] = -1;
       tv[k][0] = tv[k][1] = tv[k][2] = -1;
-      sd[k] = d2[k] = 0.0;
       if (tr < 0) continue;
       const TriDev& Tt = mt.tri[tr];
       TriGeo g;
@@ -1300,8 +1317,8 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
       tv[k][1] = Tt.v[1];
       tv[k][2] = Tt.v[2];
       kind[k] = g.feature;
-      sd[k] = g.s;
-      d2[k] = g.d2;
+      const bool close = g.feature == 0 ? g.s < rad : (g.d2 < rad * rad && g.d2 > 0.0);
+      if (close) near |= 1u << k;
       if (g.feature == 0) {
         fa[k] = tr;
       } else if (g.feature == 1) {
@@ -1312,14 +1329,17 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
         fa[k] = Tt.v[g.a];
       }
     }
+    // which slots carry a contact (the arrays above end here)
+    unsigned used = 0u, contact = 0u;
 #pragma unroll
     for (int k = 0; k < kMeshSlots; ++k) {
       if (tri[k] < 0) continue;
+      used |= 1u << k;
       const WallDev& W = walls[wl[k]];
-      bool contact = false;
+      bool c = false;
       if (t >= W.t_on && t < W.t_off) {
         if (kind[k] == 0) {
-          contact = sd[k] < rad;
+          c = (near >> k) & 1u;
         } else {
           bool dropped = false, owner = true;
 #pragma unroll
@@ -1331,27 +1351,34 @@ k_mesh(StepParams sp, const PairCoef* __restrict__ pwc, const WallDev* __restric
             if (has_a && (kind[k] == 2 || has_b) && !same) dropped = true;
             if (j < k && same) owner = false;
           }
-          contact = !dropped && owner && d2[k] < rad * rad && d2[k] > 0.0;
+          c = !dropped && owner && ((near >> k) & 1u);
         }
       }
+      if (c) contact |= 1u << k;
+    }
+    // the law for each contact, geometry evaluated again
+#pragma unroll 1
+    for (int k = 0; k < kMeshSlots; ++k) {
+      if (!((used >> k) & 1u)) continue;
       const int64_t h = (int64_t)(3 * k) * n + i;
-      if (!contact) {
+      if (!((contact >> k) & 1u)) {
         ms.hist[h] = 0.0;
         ms.hist[h + n] = 0.0;
         ms.hist[h + 2 * (int64_t)n] = 0.0;
         continue;
       }
+      const TriDev& Tt = mt.tri[ms.tri[(int64_t)k * n + i]];
+      const WallDev& W = walls[Tt.wall];
       TriGeo g;
-      tri_closest(mt.tri[tri[k]], W.vel, t, x, g);
+      tri_closest(Tt, W.vel, t, x, g);
       double gn[3], gdn;
-      if (kind[k] == 0) {
-        const double* tn = mt.tri[tri[k]].n;
-        gn[0] = -tn[0];
-        gn[1] = -tn[1];
-        gn[2] = -tn[2];
-        gdn = rad - sd[k];
+      if (g.feature == 0) {
+        gn[0] = -Tt.n[0];
+        gn[1] = -Tt.n[1];
+        gn[2] = -Tt.n[2];
+        gdn = rad - g.s;
       } else {
-        const double dist = sqrt(d2[k]);
+        const double dist = sqrt(g.d2);
         gn[0] = (g.q[0] - x[0]) / dist;
         gn[1] = (g.q[1] - x[1]) / dist;
         gn[2] = (g.q[2] - x[2]) / dist;

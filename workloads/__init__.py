@@ -164,6 +164,35 @@ def frustum_mesh(axis_point, radius0, slope, s_min, s_max, segments=48, rings=4,
                 axis_point=tuple(c), omega=(0.0, 0.0, float(omega)))
 
 
+def drum_mesh(radius, x0, x1, segments=256, rings=64, material=0, omega=0.0):
+    """Inside of the cylinder of the given radius around the x axis, x in
+    [x0, x1], as a triangle mesh (`segments` corners around, `rings` + 1
+    rings, normals towards the axis), spinning at omega about the x axis."""
+    verts, tris = [], []
+    for r in range(rings + 1):
+        x = x0 + (x1 - x0) * r / rings
+        for k in range(segments):
+            a = 2 * math.pi * k / segments
+            verts.append((x, radius * math.cos(a), radius * math.sin(a)))
+    for r in range(rings):
+        for k in range(segments):
+            a0 = r * segments + k
+            a1 = r * segments + (k + 1) % segments
+            b0, b1 = a0 + segments, a1 + segments
+            tris += [(a0, b1, a1), (a0, b0, b1)]
+    return mesh(np.array(verts), np.array(tris), material, axis_point=(0.0, 0.0, 0.0),
+                omega=(float(omega), 0.0, 0.0))
+
+
+def meshed_drum_scene(n=1_000_000, segments=256, rings=64, **kw):
+    """The rotating drum with its cylinder replaced by a spinning triangle
+    mesh (the end planes stay analytic)."""
+    sc = drum_scene(n=n, **kw)
+    g = sc["geometry"]
+    m = drum_mesh(g["R"], -g["L"] / 2, g["L"] / 2, segments, rings, omega=g["omega"])
+    return dict(sc, name=f"meshed_drum_{n}", walls=[m] + sc["walls"][1:])
+
+
 def box_walls(lo, hi, material=0):
     """Six planes bounding [lo, hi], normals pointing inwards."""
     walls = []
