@@ -237,3 +237,62 @@ def test_resume_with_mesh_walls_is_bitwise_exact(Dem):
         ma, da = a.get_mesh_contacts()
         mb, db = b.get_mesh_contacts()
         assert np.array_equal(ma, mb) and np.array_equal(da, db)
+
+
+def test_meshes_in_a_batch(Dem):
+    """Three instances with different meshes (a box, a roof and pyramid, a
+    drum) in one context: each follows its own oracle, with its own wall and
+    triangle numbering."""
+    scenes = [meshed_box(), roof_and_pyramid(), meshed_drum()]
+    b = Dem.from_scenes(scenes)
+    orc = [oracle_from_scene(sc) for sc in scenes]
+    for chunk in (1, 29):
+        b.step(chunk)
+        for k, o in enumerate(orc):
+            o.step(chunk)
+            gm, gd = b.get_mesh_contacts(k)
+            om, od = o.mesh_contacts()
+            assert np.array_equal(gm, om), k
+            Fg, _ = b.get_forces(k)
+            Fo, _, S = o.forces()
+            ef = np.max(np.linalg.norm(Fg - Fo, axis=1) /
+                        (np.linalg.norm(Fo, axis=1) + S + 1e-300))
+            assert ef <= 1e-9, (k, ef)
+
+
+def test_euler_integrator_with_meshes(Dem):
+    sc = meshed_box()
+    sc = dict(sc, config=dict(sc["config"], integrator="euler"))
+    g, o = Dem.from_scene(sc), oracle_from_scene(sc)
+    R = sc["particles"]["radius"]
+    for chunk in (1, 19, 30):
+        g.step(chunk)
+        o.step(chunk)
+        sets_equal(g, o)
+        ef, et = force_err(g, o, R)
+        assert ef <= 1e-9 and et <= 1e-9
+    assert np.max(np.abs(g.get_state()["pos"] - o.state()["pos"])) <= 1e-12
+
+
+def test_dynamic_schedule_with_a_translating_mesh(Dem):
+    """Spheres at rest and a triangulated piston that starts beyond the
+    search radius: only the mesh's motion triggers the searches that find
+    it; equal to the oracle searching every step."""
+    R = 1.5e-3
+    ys, zs = np.meshgrid(np.arange(4) * 2.2 * R, np.arange(4) * 2.2 * R, indexing="ij")
+    pos = np.stack([np.full(16, 0.01 + R + 3e-3), ys.ravel(), zs.ravel()], 1)
+    Vx = np.array([(0.01, -0.02, -0.02), (0.01, 0.03, -0.02), (0.01, 0.03, 0.03),
+                   (0.01, -0.02, 0.03)])
+    plate = W.mesh(Vx, np.array([(0, 1, 2), (0, 2, 3)]), velocity=(2.0, 0.0, 0.0))
+    cfg = W._cfg(1e-6, (0.0, -0.05, -0.05), (0.06, 0.05, 0.05), K=1, gravity=(0, 0, 0))
+    sc = dict(name="mesh_piston", config=cfg, materials=[dict(W.BOX_MATERIAL)], walls=[plate],
+              particles=W._particles(pos, R))
+    o = oracle_from_scene(sc)
+    g = Dem.from_scene(dict(sc, config=dict(cfg, rebuild_interval=0)))
+    for chunk in (1000, 2000):
+        g.step(chunk)
+        o.step(chunk)
+    sg, so = g.get_state(), o.state()
+    assert np.max(sg["vel"][:, 0]) > 2.0
+    assert np.max(np.abs(sg["pos"] - so["pos"])) <= 1e-12
+    assert 5 < g.get_stats()["n_rebuilds"] < 750
