@@ -67,7 +67,7 @@ def load_traffic(precision):
 
 
 def measure(args, precision, scene, label=None, autotune=False, force_block=0, warmup=None,
-            steps=None):
+            steps=None, keep_state=False):
     import torch
     from paper_2106_09576_amd import Dem
 
@@ -140,6 +140,8 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0, w
     )
     log(f"{precision}: {res['value']:.4g} particle-steps/s, {res['ms_per_step']:.4f} ms/step, "
         f"force kernel {force_ms:.4f} ms ({achieved:.0f} GB/s algorithmic)")
+    if keep_state:
+        res["_state"] = sim.get_state()
     sim.close()
     return res
 
@@ -299,22 +301,51 @@ def copy_bandwidth():
     return gbs
 
 
-def cpu_baseline(args, scene):
-    """The FP64 oracle (plain C, single thread) on a bounded sample: the same
-    1M-sphere drum from its initial state, a few steps including one search."""
+def cpu_baseline(args, scene, settled, precs):
+    """The FP64 oracle (plain C, single thread) on a bounded sample: the 1M
+    drum from the settled state the FP64 headline leg ended in (tangential
+    overlaps zero), a few steps after the initial contact search.  The GPU
+    runs the same steps from the same state in each precision, and the error
+    of its forces, torques and positions against the oracle is reported
+    with the baseline."""
+    import numpy as np
     from oracle import oracle_from_scene
-    log("cpu baseline: building oracle (initial search)")
-    o = oracle_from_scene(scene)
+    from paper_2106_09576_amd import Dem
+    a = settled["active"].astype(bool)
+    sc = dict(scene, particles={k: np.ascontiguousarray(v[a]) for k, v in
+                                dict(scene["particles"], pos=settled["pos"], vel=settled["vel"],
+                                     omega=settled["omega"]).items()})
+    n = int(a.sum())
+    log(f"cpu baseline: building oracle on the settled drum ({n} spheres, initial search)")
+    o = oracle_from_scene(sc)
     steps = args.cpu_steps
     log(f"cpu baseline: timing {steps} oracle steps")
     t0 = time.perf_counter()
     o.step(steps)
     t1 = time.perf_counter()
-    n = scene["particles"]["pos"].shape[0]
-    sample = (f"FP64 oracle, 1 thread, same 1M-sphere drum from its initial lattice state, "
-              f"steps 1-{steps} (search at step 20), {t1 - t0:.1f} s")
+    Fo, To, S = o.forces()
+    xo = o.state()["pos"]
+    R = sc["particles"]["radius"]
+    err = {}
+    for p in precs:
+        g = Dem.from_scene(sc, precision=p)
+        g.step(steps)
+        Fg, Tg = g.get_forces()
+        xg = g.get_state()["pos"]
+        g.close()
+        ef = np.max(np.linalg.norm(Fg - Fo, axis=1) / (np.linalg.norm(Fo, axis=1) + S + 1e-300))
+        et = np.max(np.linalg.norm(Tg - To, axis=1) /
+                    (np.linalg.norm(To, axis=1) + S * R + 1e-300))
+        err[p] = {"force_rel_max": float(ef), "torque_rel_max": float(et),
+                  "pos_abs_max_m": float(np.max(np.abs(xg - xo)))}
+    log(f"cpu baseline: {n * steps / (t1 - t0):.3g} particle-steps/s; GPU vs oracle {err}")
+    sample = (f"FP64 oracle, 1 thread, the 1M-sphere drum from the settled state of the FP64 "
+              f"headline leg (tangential overlaps zero), steps 1-{steps} after the initial "
+              f"search, {t1 - t0:.1f} s")
     return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle", "sample": sample}
+            "kind": "oracle", "sample": sample,
+            "gpu_error_vs_oracle": {"steps": steps, "per_particle": "|dF| / (|F| + sum of "
+                                    "contact |F|), torques with lever arm R", **err}}
 
 
 def main():
@@ -324,7 +355,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20000)
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-small", action="store_true",
@@ -376,7 +407,10 @@ def main():
     # headline run is reproducible: displacement-triggered search, 64-thread
     # force workgroups, cell edge = r_s
     main_scene = dict(scene, config=dict(scene["config"], rebuild_interval=0))
-    results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK) for p in precs}
+    results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK, keep_state=True)
+               for p in precs}
+    states = {p: results[p].pop("_state") for p in precs}
+    settled = states.get("fp64", states[precs[0]])
     copy_gbs = copy_bandwidth()
     main_p = "fp64" if "fp64" in results else precs[0]
     r = results[main_p]
@@ -456,7 +490,7 @@ def main():
     if not args.skip_small:
         out["small_box"] = measure_small_box(args)
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(args, scene)
+        out["cpu_baseline"] = cpu_baseline(args, scene, settled, precs)
     print(json.dumps(out), flush=True)
 
 
