@@ -681,8 +681,8 @@ int commit(dem_ctx* c);
 // the cells its own grown box overlaps (ascending triangle order), so that
 // the cell of a particle centre lists every triangle that can be its
 // candidate.  Sets the mesh fields of the instances' walls.
-void build_meshes(dem_ctx* c, std::vector<TriDev>* htri, std::vector<int>* hcell,
-                  std::vector<int>* hcell_tri) {
+int build_meshes(dem_ctx* c, std::vector<TriDev>* htri, std::vector<int>* hcell,
+                 std::vector<int>* hcell_tri) {
   c->tri_wall.clear();
   c->tri_local.clear();
   for (Instance& I : c->inst) {
@@ -763,6 +763,10 @@ void build_meshes(dem_ctx* c, std::vector<TriDev>* htri, std::vector<int>* hcell
             for (int64_t x = a[0]; x <= b[0]; ++x)
               lists[(size_t)(x + nc[0] * (y + nc[1] * z))].push_back(f);
       }
+      size_t entries = hcell_tri->size();
+      for (const std::vector<int>& li : lists) entries += li.size();
+      if (entries > ((size_t)1 << 30))
+        return set_err(DEM_EINVAL, "mesh grids too large (%zu cell entries)", entries);
       W.cell_base = (int)hcell->size();
       for (int64_t q = 0; q < ncell; ++q) {
         hcell->push_back((int)hcell_tri->size());
@@ -771,6 +775,7 @@ void build_meshes(dem_ctx* c, std::vector<TriDev>* htri, std::vector<int>* hcell
       hcell->push_back((int)hcell_tri->size());
     }
   }
+  return DEM_OK;
 }
 
 // Translating walls: a wall may move at most half the skin between two
@@ -988,7 +993,7 @@ int commit(dem_ctx* c) {
   }
   std::vector<TriDev> htri;
   std::vector<int> hcell, hcell_tri;
-  build_meshes(c, &htri, &hcell, &hcell_tri);
+  if (int rc = build_meshes(c, &htri, &hcell, &hcell_tri)) return rc;
   c->dynamic = c->cfg.rebuild_interval == 0;
   double ihs_max = 0.0, rate0 = 0.0, ihs_min = HUGE_VAL;
   bool all_skins = true;
