@@ -567,7 +567,9 @@ def dam_break_scene(n=1_280_000, d=1.0e-3, length=0.4, height=0.2, t_dam=0.5, se
     layers = n / per_layer + 2
     while True:
         top = min(height - c, c + a * layers)
-        g = jittered_lattice((c, c, c), (length / 2 - c, top, depth - c), a, jitter * d, rng)
+        jd = jitter * d  # lattice inset by the jitter so that no site is pushed out
+        g = jittered_lattice((c + jd, c + jd, c + jd), (length / 2 - c - jd, top, depth - c - jd),
+                             a, jd, rng)
         keep = ((g[:, 0] >= c) & (g[:, 0] <= length / 2 - c) & (g[:, 1] >= c) &
                 (g[:, 2] >= c) & (g[:, 2] <= depth - c))
         g = g[keep]
