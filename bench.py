@@ -456,41 +456,47 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         out["mixed_vs_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
-    if not args.skip_fixed:
+    def fixed_k20():
         fres = {p: measure(args, p, scene, label=f"{p} K=20") for p in precs}
-        out["fixed_k20"] = {
-            "workload": "same drum, contact search every 20 steps, 256-thread force workgroups",
-            "results": fres,
-        }
-    if not args.no_autotune:
+        return {"workload": "same drum, contact search every 20 steps, 256-thread force "
+                            "workgroups", "results": fres}
+
+    def autotuned():
         tres = {p: measure(args, p, scene, label=f"{p} autotuned", autotune=True) for p in precs}
-        out["autotuned"] = {
-            "workload": "same drum; force block size, cell edge and search schedule picked by "
-                        "dem_autotune after the settling steps",
-            "results": tres,
-        }
-    if not args.skip_batched:
+        return {"workload": "same drum; force block size, cell edge and search schedule picked "
+                            "by dem_autotune after the settling steps", "results": tres}
+
+    def batched():
         b = {p: measure_batched(args, p) for p in precs}
-        out["batched"] = {
-            "workload": ("256 independent rotating drums in one context, 2k-50k spheres each "
-                         "(log-uniform), d=3mm, mu U[0.1,0.5], 0.5-3 rad/s, 35% fill, dt=5e-6 s, "
-                         f"after {args.batch_warmup} settling steps; "
-                         + ("autotuned block size, cell edge and search schedule"
-                            if not args.no_autotune else "search every 20 steps")),
-            "results": b,
-        }
+        res = {"workload": ("256 independent rotating drums in one context, 2k-50k spheres each "
+                            "(log-uniform), d=3mm, mu U[0.1,0.5], 0.5-3 rad/s, 35% fill, "
+                            f"dt=5e-6 s, after {args.batch_warmup} settling steps; "
+                            + ("autotuned block size, cell edge and search schedule"
+                               if not args.no_autotune else "search every 20 steps")),
+               "results": b}
         if "fp32" in b and "fp64" in b:
-            out["batched"]["fp32_vs_fp64"] = b["fp32"]["value"] / b["fp64"]["value"]
-    if not args.skip_variants:
-        out["model_variants"] = measure_variants(args, scene)
-    if not args.skip_mesh:
-        out["meshed_drum"] = measure_meshed_drum(args)
-    if not args.skip_dam:
-        out["dam_break"] = measure_dam_break(args, precs)
-    if not args.skip_small:
-        out["small_box"] = measure_small_box(args)
-    if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(args, scene, settled, precs)
+            res["fp32_vs_fp64"] = b["fp32"]["value"] / b["fp64"]["value"]
+        return res
+
+    # the further legs: a failure is recorded in its own entry and the line
+    # is still printed
+    legs = [("fixed_k20", not args.skip_fixed, fixed_k20),
+            ("autotuned", not args.no_autotune, autotuned),
+            ("batched", not args.skip_batched, batched),
+            ("model_variants", not args.skip_variants, lambda: measure_variants(args, scene)),
+            ("meshed_drum", not args.skip_mesh, lambda: measure_meshed_drum(args)),
+            ("dam_break", not args.skip_dam, lambda: measure_dam_break(args, precs)),
+            ("small_box", not args.skip_small, lambda: measure_small_box(args)),
+            ("cpu_baseline", not args.skip_cpu,
+             lambda: cpu_baseline(args, scene, settled, precs))]
+    for name, on, fn in legs:
+        if not on:
+            continue
+        try:
+            out[name] = fn()
+        except Exception as e:  # noqa: BLE001 (any failure of a side leg)
+            log(f"{name} failed: {e}")
+            out[name] = {"error": str(e)}
     print(json.dumps(out), flush=True)
 
 
