@@ -392,7 +392,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU domain "
-              f"decomposition is a design, not part of this build", file=sys.stderr)
+              f"decomposition is a design, not part of this library", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
