@@ -72,7 +72,7 @@ def meshed_hopper():
 def roof_and_pyramid(n_side=24, seed=5):
     """A roof (ridge along y) and a pyramid side by side on a floor, spheres
     raining onto them from a lattice just above, with random velocities and
-    spins."""
+    spins; the pyramid switches off at step 80."""
     rng = np.random.default_rng(seed)
     R = 1.5e-3
     a = math.radians(30.0)
@@ -98,7 +98,8 @@ def roof_and_pyramid(n_side=24, seed=5):
                            -0.3 - 0.1 * rng.random(len(pts))])
     om = rng.uniform(-30, 30, (len(pts), 3))
     cfg = W._cfg(1e-5, (-0.06, -0.06, -0.06), (0.16, 0.06, 0.06), K=10)
-    walls = [W.mesh(V1, T1), W.mesh(V2, T2), W.plane((0, 0, -0.03), (0, 0, 1))]
+    # the pyramid is a floating wall: it disappears at step 80
+    walls = [W.mesh(V1, T1), W.mesh(V2, T2, t_off=80e-5), W.plane((0, 0, -0.03), (0, 0, 1))]
     return dict(name="roof_pyramid", config=cfg, materials=[dict(W.BOX_MATERIAL)], walls=walls,
                 particles=W._particles(pts, R, vel, om))
 
