@@ -1063,9 +1063,13 @@ __device__ __forceinline__ double force_particle(
   const int len = l.rowlen[i];
   const int max_nb = sp.max_nb;
   const int64_t cap = l.cap;
+  // the index of entry k + 1 is loaded while entry k is worked on (the
+  // row walk is a chain of dependent loads; one index ahead costs one VGPR)
+  int jr_next = len > 0 ? l.nbr[nbr_entry(i, 0, max_nb)] : 0;
   for (int k = 0; k < len; ++k) {
     const int64_t e = nbr_entry(i, k, max_nb);
-    const int jr = l.nbr[e];
+    const int jr = jr_next;
+    if (k + 1 < len) jr_next = l.nbr[e + 64];  // entry (i, k + 1)
     const int j = jr & kIndexMask;
     const double4 xj = tile.pos(in, j);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
