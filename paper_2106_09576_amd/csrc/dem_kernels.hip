@@ -1034,7 +1034,8 @@ __device__ __forceinline__ double force_particle(
     const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
     double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
     const int* __restrict__ flags, const bool want_drift, const int* __restrict__ xsel,
-    const double4* __restrict__ Fx, const double4* __restrict__ Tx, const TileT& tile) {
+    const double4* __restrict__ Fx, const double4* __restrict__ Tx, const TileT& tile,
+    const int len, const int jr0) {
   const int n = sp.n;
   double4 xi = tile.pos(in, i);
   double4 vi = tile.vel(in, i);
@@ -1060,12 +1061,12 @@ __device__ __forceinline__ double force_particle(
   const double dt = sp.dt;
   double F[3] = {0.0, 0.0, 0.0};
   double T[3] = {0.0, 0.0, 0.0};
-  const int len = l.rowlen[i];
   const int max_nb = sp.max_nb;
   const int64_t cap = l.cap;
   // the index of entry k + 1 is loaded while entry k is worked on (the
-  // row walk is a chain of dependent loads; one index ahead costs one VGPR)
-  int jr_next = len > 0 ? l.nbr[nbr_entry(i, 0, max_nb)] : 0;
+  // row walk is a chain of dependent loads; one index ahead costs one VGPR);
+  // the row length and entry 0 come from the caller
+  int jr_next = jr0;
   for (int k = 0; k < len; ++k) {
     const int64_t e = nbr_entry(i, k, max_nb);
     const int jr = jr_next;
@@ -1218,6 +1219,13 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
         const double4* __restrict__ Tx) {
   const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
+  // the row length and the first row entry do not depend on the tile: their
+  // loads are issued before it is staged (entry 0 exists for every row)
+  int len = 0, jr0 = 0;
+  if (i < sp.n) {
+    len = l.rowlen[i];
+    jr0 = l.nbr[nbr_entry(i, 0, sp.max_nb)];
+  }
   __shared__ Tile<BS> tile;
   tile.stage(in, info, b0, sp.n);
   __syncthreads();
@@ -1225,7 +1233,7 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   if (i < sp.n)
     d = force_particle<R, MODE, MODEL>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
                                        To, clock, step_rel, flags, drift != nullptr, xsel, Fx,
-                                       Tx, tile);
+                                       Tx, tile, len, jr0);
   if (drift) wave_max_to(drift, d, BS / 64);
 }
 
