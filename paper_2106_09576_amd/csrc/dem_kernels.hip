@@ -1072,6 +1072,14 @@ __device__ __forceinline__ double force_particle(
     const int jr = jr_next;
     if (k + 1 < len) jr_next = l.nbr[e + 64];  // entry (i, k + 1)
     const int j = jr & kIndexMask;
+    // a pair touching at the last evaluation most likely still touches: its
+    // history is loaded together with the neighbour's position
+    double dtl[3] = {0.0, 0.0, 0.0};
+    if (jr & kTouchedBit) {
+      dtl[0] = l.hist[e];
+      dtl[1] = l.hist[cap + e];
+      dtl[2] = l.hist[2 * cap + e];
+    }
     const double4 xj = tile.pos(in, j);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
     const double d2 = (dx * dx + dy * dy) + dz * dz;
@@ -1080,12 +1088,6 @@ __device__ __forceinline__ double force_particle(
       const double4 vj = tile.vel(in, j);
       const double4 wj = tile.omg(in, j);
       const int tj = tile.info(info, j) & kTypeMask;
-      double dtl[3] = {0.0, 0.0, 0.0};
-      if (jr & kTouchedBit) {
-        dtl[0] = l.hist[e];
-        dtl[1] = l.hist[cap + e];
-        dtl[2] = l.hist[2 * cap + e];
-      }
       double Fi[3], Mi[3];
       pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       l.hist[e] = dtl[0];
