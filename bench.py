@@ -301,6 +301,24 @@ def copy_bandwidth():
     return gbs
 
 
+def host_cpu():
+    """Model name of the host's processor and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "cpus_usable": usable, "cpus_online": os.cpu_count()}
+
+
 def cpu_baseline(args, scene, settled, precs):
     """The FP64 oracle (plain C, single thread) on a bounded sample: the 1M
     drum from the settled state the FP64 headline leg ended in (tangential
@@ -343,7 +361,7 @@ def cpu_baseline(args, scene, settled, precs):
               f"headline leg (tangential overlaps zero), steps 1-{steps} after the initial "
               f"search, {t1 - t0:.1f} s")
     return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle", "sample": sample,
+            "kind": "oracle", "sample": sample, "host_cpu": host_cpu(),
             "gpu_error_vs_oracle": {"steps": steps, "per_particle": "|dF| / (|F| + sum of "
                                     "contact |F|), torques with lever arm R", **err}}
 
