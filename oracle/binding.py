@@ -84,6 +84,7 @@ def _load():
         lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
         lib.ora_get_forces.argtypes = [P, D, D]
         lib.ora_get_force_scale.argtypes = [P, D]
+        lib.ora_get_term_scale.argtypes = [P, D]
         lib.ora_num_contacts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         lib.ora_get_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
                                          C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]
@@ -258,6 +259,13 @@ class OracleSim:
         _check(self._lib.ora_get_forces(self._h, _dp(F), _dp(T)), "ora_get_forces")
         _check(self._lib.ora_get_force_scale(self._h, _dp(S)), "ora_get_force_scale")
         return F, T, S
+
+    def term_scale(self):
+        """Per particle: sum over its contacts of the magnitudes of the spring
+        and dashpot terms of the last evaluation (before the Coulomb limit)."""
+        S2 = np.empty(self.n)
+        _check(self._lib.ora_get_term_scale(self._h, _dp(S2)), "ora_get_term_scale")
+        return S2
 
     def contacts(self):
         npairs = C.c_int64(); nw = C.c_int64()

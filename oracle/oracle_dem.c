@@ -126,7 +126,7 @@ struct ora_sim {
   ora_material mat[ORA_MAX_TYPES];
   int mat_set[ORA_MAX_TYPES];
   int64_t n;
-  double *x, *v, *w, *R, *m, *I, *F, *T, *S, *xref;
+  double *x, *v, *w, *R, *m, *I, *F, *T, *S, *S2, *xref;
   int32_t* type;
   uint8_t* active;
   double dmax, rs, rs2, h, skin;
@@ -191,7 +191,10 @@ typedef struct {
  * the rolling velocity vroll (V_omega of the table of rolling models), the
  * lever arms Ri, Rj and the tangential overlap (updated in place).
  * Outputs: the force on i (normal + tangential), the torques on i and j, and
- * |F^n + F^t| for the force scale.
+ * two force scales: fmag[0] = |F^n + F^t| and fmag[1] = the sum of the
+ * magnitudes of the four terms of Eqs. (normal_force) and (tangential_force)
+ * before the Coulomb limit (spring and dashpot of each), which stays large
+ * where the spring and the dashpot nearly cancel.
  */
 static void contact_law(const ora_contact_props* cp, const ora_config* cfg, double dn,
                         const double* n, const double* vij, const double* wrel,
@@ -238,6 +241,8 @@ static void contact_law(const ora_contact_props* cp, const ora_config* cfg, doub
   }
   double fn = vnorm(Fn);
   double ft = vnorm(Ft);
+  const double terms = kn * dn + fabs(etan) * fabs(vn) + kt * vnorm(delta_t) +
+                       fabs(etat) * vnorm(vrt);
   /* Coulomb criterion, Eqs. (coulomb_overlap)-(coulomb_overlap3) */
   if (ft >= cp->mu * fn && ft > 0.0) {
     for (int k = 0; k < 3; ++k) {
@@ -272,7 +277,8 @@ static void contact_law(const ora_contact_props* cp, const ora_config* cfg, doub
     Mi[k] = Ri * nxft[k] + Mr[k];
     Mj[k] = Rj * nxft[k] - Mr[k];
   }
-  *fmag = vnorm(Fsum);
+  fmag[0] = vnorm(Fsum);
+  fmag[1] = terms;
 }
 
 static void pp_props(const ora_sim* s, int ti, int tj, double mi, double mj, double Ri,
@@ -305,7 +311,7 @@ static int pp_contact(const ora_sim* s, const double* xi, const double* xj,
   double d2 = vdot(dx, dx);
   double rsum = Ri + Rj;
   for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = Mj[k] = 0.0;
-  *fmag = 0.0;
+  fmag[0] = fmag[1] = 0.0;
   if (!(d2 < rsum * rsum)) {
     delta_t[0] = delta_t[1] = delta_t[2] = 0.0; /* contact ended */
     return 0;
@@ -502,7 +508,7 @@ static int pw_contact(const ora_sim* s, const ora_wall* W, double t, const doubl
                       const double* v, const double* w, double R, double m, int ti,
                       double* delta_t, double* Fi, double* Mi, double* fmag) {
   for (int k = 0; k < 3; ++k) Fi[k] = Mi[k] = 0.0;
-  *fmag = 0.0;
+  fmag[0] = fmag[1] = 0.0;
   const ora_wall Wt = wall_at(W, t);
   W = &Wt;
   ora_wgeo g;
@@ -684,14 +690,15 @@ static void mesh_contacts(ora_sim* s, const ora_wall* W0, double t, ora_mpair* M
       for (int c = 0; c < 3; ++c) n[c] = (G[k].q[c] - x[c]) / dist;
       dn = R - dist;
     }
-    double Fi[3], Mi[3], fm;
+    double Fi[3], Mi[3], fm[2];
     wall_law(s, &Wt, &s->v[3 * i], &s->w[3 * i], R, s->m[i], s->type[i], n, dn, G[k].q,
-             M[k].dt, Fi, Mi, &fm);
+             M[k].dt, Fi, Mi, fm);
     for (int c = 0; c < 3; ++c) {
       s->F[3 * i + c] += Fi[c];
       s->T[3 * i + c] += Mi[c];
     }
-    s->S[i] += fm;
+    s->S[i] += fm[0];
+    s->S2[i] += fm[1];
   }
   free(G);
   free(Fe);
@@ -955,31 +962,35 @@ static void compute_forces(ora_sim* s, double t) {
   memset(s->F, 0, sizeof(double) * n3);
   memset(s->T, 0, sizeof(double) * n3);
   memset(s->S, 0, sizeof(double) * (size_t)s->n);
+  memset(s->S2, 0, sizeof(double) * (size_t)s->n);
   for (int64_t p = 0; p < s->npairs; ++p) {
     int64_t i = s->pairs[p].i, j = s->pairs[p].j;
-    double Fi[3], Mi[3], Mj[3], fm;
+    double Fi[3], Mi[3], Mj[3], fm[2];
     pp_contact(s, &s->x[3 * i], &s->x[3 * j], &s->v[3 * i], &s->v[3 * j], &s->w[3 * i],
                &s->w[3 * j], s->R[i], s->R[j], s->m[i], s->m[j], s->type[i], s->type[j],
-               s->pairs[p].dt, Fi, Mi, Mj, &fm);
+               s->pairs[p].dt, Fi, Mi, Mj, fm);
     for (int k = 0; k < 3; ++k) {
       s->F[3 * i + k] += Fi[k];
       s->F[3 * j + k] -= Fi[k];
       s->T[3 * i + k] += Mi[k];
       s->T[3 * j + k] += Mj[k];
     }
-    s->S[i] += fm;
-    s->S[j] += fm;
+    s->S[i] += fm[0];
+    s->S[j] += fm[0];
+    s->S2[i] += fm[1];
+    s->S2[j] += fm[1];
   }
   for (int64_t p = 0; p < s->nwpairs; ++p) {
     int64_t i = s->wpairs[p].i;
-    double Fi[3], Mi[3], fm;
+    double Fi[3], Mi[3], fm[2];
     pw_contact(s, &s->walls[s->wpairs[p].w], t, &s->x[3 * i], &s->v[3 * i], &s->w[3 * i],
-               s->R[i], s->m[i], s->type[i], s->wpairs[p].dt, Fi, Mi, &fm);
+               s->R[i], s->m[i], s->type[i], s->wpairs[p].dt, Fi, Mi, fm);
     for (int k = 0; k < 3; ++k) {
       s->F[3 * i + k] += Fi[k];
       s->T[3 * i + k] += Mi[k];
     }
-    s->S[i] += fm;
+    s->S[i] += fm[0];
+    s->S2[i] += fm[1];
   }
   /* mesh walls: the candidates of one particle and one mesh together */
   for (int64_t p = 0; p < s->nmpairs;) {
@@ -1070,9 +1081,9 @@ int ora_create(const ora_config* cfg, ora_sim** out) {
 
 static void free_particles(ora_sim* s) {
   free(s->x); free(s->v); free(s->w); free(s->R); free(s->m); free(s->I);
-  free(s->F); free(s->T); free(s->S); free(s->xref); free(s->type); free(s->active);
+  free(s->F); free(s->T); free(s->S); free(s->S2); free(s->xref); free(s->type); free(s->active);
   free(s->pairs); free(s->wpairs); free(s->mpairs);
-  s->x = s->v = s->w = s->R = s->m = s->I = s->F = s->T = s->S = s->xref = NULL;
+  s->x = s->v = s->w = s->R = s->m = s->I = s->F = s->T = s->S = s->S2 = s->xref = NULL;
   s->type = NULL; s->active = NULL; s->pairs = NULL; s->wpairs = NULL; s->mpairs = NULL;
   s->npairs = s->nwpairs = s->nmpairs = 0;
 }
@@ -1118,10 +1129,11 @@ int ora_set_particles(ora_sim* s, int64_t n, const double* pos, const double* ve
   s->m = (double*)calloc(n1, sizeof(double));
   s->I = (double*)calloc(n1, sizeof(double));
   s->S = (double*)calloc(n1, sizeof(double));
+  s->S2 = (double*)calloc(n1, sizeof(double));
   s->type = (int32_t*)calloc(n1, sizeof(int32_t));
   s->active = (uint8_t*)calloc(n1, 1);
   if (!s->x || !s->v || !s->w || !s->F || !s->T || !s->xref || !s->R || !s->m || !s->I ||
-      !s->S || !s->type || !s->active) {
+      !s->S || !s->S2 || !s->type || !s->active) {
     free_particles(s);
     return ORA_ENOMEM;
   }
@@ -1385,6 +1397,13 @@ int ora_get_force_scale(ora_sim* s, double* scale) {
   return ORA_OK;
 }
 
+int ora_get_term_scale(ora_sim* s, double* scale) {
+  if (!s || !scale) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  memcpy(scale, s->S2, sizeof(double) * (size_t)s->n);
+  return ORA_OK;
+}
+
 int ora_num_contacts(ora_sim* s, int64_t* n_pairs, int64_t* n_wall) {
   if (!s) return ORA_EINVAL;
   if (n_pairs) *n_pairs = s->npairs;
@@ -1492,9 +1511,9 @@ int ora_pair_force(ora_sim* s, const double xi[3], const double xj[3],
     return ORA_EINVAL;
   double mi = s->mat[ti].density * (4.0 / 3.0) * PI * Ri * Ri * Ri;
   double mj = s->mat[tj].density * (4.0 / 3.0) * PI * Rj * Rj * Rj;
-  double fm;
+  double fm[2];
   int t = pp_contact(s, xi, xj, vi, vj, wi, wj, Ri, Rj, mi, mj, ti, tj, delta_t, F_i, M_i,
-                     M_j, &fm);
+                     M_j, fm);
   if (touching) *touching = t;
   return ORA_OK;
 }

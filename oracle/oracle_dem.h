@@ -87,6 +87,10 @@ int ora_get_state(ora_sim* s, double* pos, double* vel, double* omega, uint8_t* 
 int ora_get_forces(ora_sim* s, double* force, double* torque);
 /* sum over the particle's contacts of |F^n + F^t| of the last evaluation */
 int ora_get_force_scale(ora_sim* s, double* scale);
+/* sum over the particle's contacts of the magnitudes of the spring and
+   dashpot terms of the normal and tangential forces (before the Coulomb
+   limit): a scale that does not shrink where spring and dashpot cancel */
+int ora_get_term_scale(ora_sim* s, double* scale);
 int ora_num_contacts(ora_sim* s, int64_t* n_pairs, int64_t* n_wall);
 int ora_get_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
                      uint8_t* touching, int64_t* n_out);
