@@ -351,6 +351,54 @@ def test_drum_1m_forces_and_sets_after_steps(drum_pair):
     assert st["n_active"] == 1_000_000
 
 
+def test_drum_1m_settled_forces_one_step_both_precisions(Dem):
+    """The state the headline benchmark times: the drum settled for 20,000
+    steps (dynamic search, 64-thread force workgroups), then one step of the
+    GPU in each precision against the oracle from the same state.  The FP32
+    law is held to the bar against the term scale (sum of the magnitudes of
+    the spring and dashpot terms): at the end of a contact the dashpot pulls
+    against the spring and the net contact force is a small difference of
+    two large terms, each rounded to FP32."""
+    sc = W.drum_scene()
+    main = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+    g = Dem.from_scene(main, precision="fp64", force_block=64)
+    for _ in range(4):
+        g.step(5000)
+    st = g.get_state()
+    g.close()
+    a = st["active"].astype(bool)
+    assert a.sum() == 1_000_000
+    snap = dict(sc, particles={k: np.ascontiguousarray(v[a]) for k, v in
+                               dict(sc["particles"], pos=st["pos"], vel=st["vel"],
+                                    omega=st["omega"]).items()})
+    o = oracle_from_scene(snap)
+    o.step(1)
+    Fo, To, S = o.forces()
+    S2 = o.term_scale()
+    R = snap["particles"]["radius"]
+    nF, nT = np.linalg.norm(Fo, axis=1), np.linalg.norm(To, axis=1)
+    for precision in ("fp64", "fp32"):
+        gp = Dem.from_scene(snap, precision=precision)
+        gp.step(1)
+        if precision == "fp64":
+            (gd, od), _ = assert_same_contacts(gp, o)
+            assert len(gd) > 4_000_000
+        Fg, Tg = gp.get_forces()
+        gp.close()
+        dF = np.linalg.norm(Fg - Fo, axis=1)
+        dT = np.linalg.norm(Tg - To, axis=1)
+        ef_net = np.max(dF / (nF + S + 1e-300))
+        ef = np.max(dF / (nF + S2 + 1e-300))
+        et = np.max(dT / (nT + S2 * R + 1e-300))
+        print("settled drum", precision, "net", ef_net, "term scale", ef, et, flush=True)
+        if precision == "fp64":
+            # the net scale amplifies the law's last-bit differences where the
+            # terms cancel (1.2e-9 on this bed); the term scale does not
+            assert ef_net <= 1e-8 and ef <= 1e-10 and et <= 1e-10
+        else:
+            assert ef <= 1e-5 and et <= 1e-5
+
+
 # ------------------------------------------------------- dynamic search trigger
 
 @pytest.mark.parametrize("integrator", ["verlet", "euler"])
