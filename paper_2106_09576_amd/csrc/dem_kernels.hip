@@ -970,6 +970,25 @@ __device__ __forceinline__ void pw_contact(const PairCoef& c, int rolling, int m
 constexpr int kTouchedBit = (int)0x80000000u;
 constexpr int kIndexMask = 0x7fffffff;
 
+// Accesses to data that only the particle's own thread touches in a force
+// launch (its row, row length, pair and wall histories, its new state) are
+// non-temporal: they are not reused from the caches within the launch, and
+// leaving L2 to the neighbour gathers, which are, made the launch 3-4 %
+// faster.
+template <typename T>
+__device__ __forceinline__ T ld_own(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_own(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+typedef double own_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_own(const double4& v, double4* p) {
+  const own_d4 w = {v.x, v.y, v.z, v.w};
+  __builtin_nontemporal_store(w, reinterpret_cast<own_d4*>(p));
+}
+
 // The states of the BS consecutive sorted particles of a force block, staged
 // in LDS: in spatial (Morton) order most neighbours of a block's particles lie
 // inside the block, and they are then read from LDS instead of through the
@@ -1070,15 +1089,15 @@ __device__ __forceinline__ double force_particle(
   for (int k = 0; k < len; ++k) {
     const int64_t e = nbr_entry(i, k, max_nb);
     const int jr = jr_next;
-    if (k + 1 < len) jr_next = l.nbr[e + 64];  // entry (i, k + 1)
+    if (k + 1 < len) jr_next = ld_own(l.nbr + e + 64);  // entry (i, k + 1)
     const int j = jr & kIndexMask;
     // a pair touching at the last evaluation most likely still touches: its
     // history is loaded together with the neighbour's position
     double dtl[3] = {0.0, 0.0, 0.0};
     if (jr & kTouchedBit) {
-      dtl[0] = l.hist[e];
-      dtl[1] = l.hist[cap + e];
-      dtl[2] = l.hist[2 * cap + e];
+      dtl[0] = ld_own(l.hist + e);
+      dtl[1] = ld_own(l.hist + cap + e);
+      dtl[2] = ld_own(l.hist + 2 * cap + e);
     }
     const double4 xj = tile.pos(in, j);
     const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
@@ -1090,10 +1109,10 @@ __device__ __forceinline__ double force_particle(
       const int tj = tile.info(info, j) & kTypeMask;
       double Fi[3], Mi[3];
       pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
-      l.hist[e] = dtl[0];
-      l.hist[cap + e] = dtl[1];
-      l.hist[2 * cap + e] = dtl[2];
-      if (!(jr & kTouchedBit)) l.nbr[e] = j | kTouchedBit;
+      st_own(dtl[0], l.hist + e);
+      st_own(dtl[1], l.hist + cap + e);
+      st_own(dtl[2], l.hist + 2 * cap + e);
+      if (!(jr & kTouchedBit)) st_own(j | kTouchedBit, l.nbr + e);
       F[0] += Fi[0];
       F[1] += Fi[1];
       F[2] += Fi[2];
@@ -1101,10 +1120,10 @@ __device__ __forceinline__ double force_particle(
       T[1] += Mi[1];
       T[2] += Mi[2];
     } else if (jr & kTouchedBit) {
-      l.hist[e] = 0.0;
-      l.hist[cap + e] = 0.0;
-      l.hist[2 * cap + e] = 0.0;
-      l.nbr[e] = j;
+      st_own(0.0, l.hist + e);
+      st_own(0.0, l.hist + cap + e);
+      st_own(0.0, l.hist + 2 * cap + e);
+      st_own(j, l.nbr + e);
     }
   }
   // walls: time of this force evaluation
@@ -1124,9 +1143,9 @@ __device__ __forceinline__ double force_particle(
       Fi[0] = Fi[1] = Fi[2] = 0.0;
       Mi[0] = Mi[1] = Mi[2] = 0.0;
     }
-    ws.hist[(int64_t)(3 * s) * n + i] = dtl[0];
-    ws.hist[(int64_t)(3 * s + 1) * n + i] = dtl[1];
-    ws.hist[(int64_t)(3 * s + 2) * n + i] = dtl[2];
+    st_own(dtl[0], ws.hist + (int64_t)(3 * s) * n + i);
+    st_own(dtl[1], ws.hist + (int64_t)(3 * s + 1) * n + i);
+    st_own(dtl[2], ws.hist + (int64_t)(3 * s + 2) * n + i);
     F[0] += Fi[0];
     F[1] += Fi[1];
     F[2] += Fi[2];
@@ -1183,9 +1202,9 @@ __device__ __forceinline__ double force_particle(
       if (want_drift) drift = drift2(vi, drift_scale(sp, inst, inf));
     }
   }
-  out.pos[i] = xi;
-  out.vel[i] = vi;
-  out.omg[i] = wi;
+  st_own(xi, out.pos + i);
+  st_own(vi, out.vel + i);
+  st_own(wi, out.omg + i);
   if (MODE != 0) {
     Fo[i] = make_double4(F[0], F[1], F[2], 0.0);
     To[i] = make_double4(T[0], T[1], T[2], 0.0);
@@ -1225,8 +1244,8 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   // loads are issued before it is staged (entry 0 exists for every row)
   int len = 0, jr0 = 0;
   if (i < sp.n) {
-    len = l.rowlen[i];
-    jr0 = l.nbr[nbr_entry(i, 0, sp.max_nb)];
+    len = ld_own(l.rowlen + i);
+    jr0 = ld_own(l.nbr + nbr_entry(i, 0, sp.max_nb));
   }
   __shared__ Tile<BS> tile;
   tile.stage(in, info, b0, sp.n);
