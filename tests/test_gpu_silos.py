@@ -6,7 +6,8 @@ Small silos (3,000 spheres at the bottom of the full geometry, a slightly
 overlapping start so that contacts exist from the first step, the outlet
 opening during the run) are compared with the oracle step by step: contact
 sets bit-exact, forces within the law's tolerance, positions after the run.
-The full 4.3M-sphere hopper silo is compared on its initial snapshot.
+The full 4.3M-sphere hopper silo is compared on its initial snapshot, the
+full 200,000-sphere wedge silo over its first 20 steps.
 """
 import numpy as np
 import pytest
@@ -110,3 +111,46 @@ def test_full_hopper_silo_initial_sets_bit_exact(Dem):
     assert nw > 10000
     g.step(20)
     assert g.get_stats()["n_active"] == sc["particles"]["pos"].shape[0]
+
+
+def test_full_wedge_silo_parity(Dem):
+    """The 200,000-sphere wedge silo (diameters uniform in [2, 3] mm, two
+    bounded inclined planes and the floating plug), with a slightly
+    overlapping start so that contacts exist at once and seeded spins:
+    sets bit-exact after the first step and after the search at step 20;
+    FP64 forces within the bar at both; the FP32 law's forces within the bar
+    (against the oracle's term scale) after the first step, from the common
+    start.  Later its trajectory is its own: the constant rolling torque
+    follows the relative spin, whose direction the FP32 rounding turns where
+    that spin is small, so a comparison at step 20 measures the drift of the
+    two runs rather than the law."""
+    sc = W.wedge_silo_scene(spacing=0.94, clearance=0.98)
+    rng = np.random.default_rng(23)
+    sc["particles"]["omega"] = rng.uniform(-20.0, 20.0, sc["particles"]["pos"].shape)
+    n = sc["particles"]["pos"].shape[0]
+    R = sc["particles"]["radius"]
+    print("wedge silo", n, "spheres", flush=True)
+    o = oracle_from_scene(sc)
+    g64 = Dem.from_scene(sc, precision="fp64")
+    g32 = Dem.from_scene(sc, precision="fp32")
+    for steps in (1, 19):
+        o.step(steps)
+        g64.step(steps)
+        g32.step(steps)
+        nt, nw = sets_equal(g64, o)
+        Fo, To, S = o.forces()
+        S2 = o.term_scale()
+        ef, et = force_err(g64, o, R)
+        F32, T32 = g32.get_forces()
+        ef32 = np.max(np.linalg.norm(F32 - Fo, axis=1) /
+                      (np.linalg.norm(Fo, axis=1) + S2 + 1e-300))
+        et32 = np.max(np.linalg.norm(T32 - To, axis=1) /
+                      (np.linalg.norm(To, axis=1) + S2 * R + 1e-300))
+        print("step", g64.get_stats()["step"], "touching", nt, "wall", nw, "fp64", ef, et,
+              "fp32 (term scale)", ef32, et32, flush=True)
+        assert nt > 20_000 and nw > 100
+        assert ef <= 1e-9 and et <= 1e-9
+        if steps == 1:
+            assert ef32 <= 1e-5 and et32 <= 1e-5
+        sets_equal(g32, o)
+    assert g64.get_stats()["n_active"] == n
