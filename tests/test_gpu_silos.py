@@ -101,16 +101,53 @@ def test_cone_wall_rejects_bad_geometry(Dem):
 def test_full_hopper_silo_initial_sets_bit_exact(Dem):
     """The 4.3M-sphere hopper silo (log-normal diameters, cone + cylinder):
     candidate pairs, touching flags and wall candidates of the initial
-    snapshot agree bit for bit."""
+    snapshot agree bit for bit.  The same silo filled more densely (lattice
+    spacing 0.8 d_max, 670,000 touching pairs, seeded spins): after one step
+    from the common start, sets bit-exact and the forces of both precisions
+    within the bars (the FP32 law against the oracle's term scale)."""
     sc = W.hopper_silo_scene(spacing=1.0, clearance=0.98)
-    print("hopper silo", sc["particles"]["pos"].shape[0], "spheres", flush=True)
+    n = sc["particles"]["pos"].shape[0]
+    print("hopper silo", n, "spheres", flush=True)
     g = Dem.from_scene(sc, precision="fp32")
     o = oracle_from_scene(sc)
     nt, nw = sets_equal(g, o)
     print("touching", nt, "wall candidates", nw, flush=True)
     assert nw > 10000
     g.step(20)
-    assert g.get_stats()["n_active"] == sc["particles"]["pos"].shape[0]
+    assert g.get_stats()["n_active"] == n
+    g.close()
+    del o
+    sc = W.hopper_silo_scene(spacing=0.8, clearance=1.0)
+    rng = np.random.default_rng(31)
+    sc["particles"]["omega"] = rng.uniform(-20.0, 20.0, sc["particles"]["pos"].shape)
+    R = sc["particles"]["radius"]
+    o = oracle_from_scene(sc)
+    g = Dem.from_scene(sc, precision="fp32")
+    g64 = Dem.from_scene(sc, precision="fp64")
+    o.step(1)
+    g.step(1)
+    g64.step(1)
+    sets_equal(g64, o)
+    Fo, To, S = o.forces()
+    S2 = o.term_scale()
+    ef, et = force_err(g64, o, R)
+
+    def term_err(Fg, Tg):
+        return (np.max(np.linalg.norm(Fg - Fo, axis=1) / (np.linalg.norm(Fo, axis=1) + S2 + 1e-300)),
+                np.max(np.linalg.norm(Tg - To, axis=1) /
+                       (np.linalg.norm(To, axis=1) + S2 * R + 1e-300)))
+
+    ef64, et64 = term_err(*g64.get_forces())
+    ef32, et32 = term_err(*g.get_forces())
+    nt = int(o.contacts()[2].sum())
+    print("dense fill, step 1: touching", nt, "fp64 net", ef, et, "term scale", ef64, et64,
+          "fp32 (term scale)", ef32, et32, flush=True)
+    assert nt > 500_000
+    # the net scale amplifies last-bit differences where spring and dashpot
+    # cancel; the term scale does not
+    assert ef <= 1e-8 and et <= 1e-8 and ef64 <= 1e-10 and et64 <= 1e-10
+    assert ef32 <= 1e-5 and et32 <= 1e-5
+    sets_equal(g, o)
 
 
 def test_full_wedge_silo_parity(Dem):
