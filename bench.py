@@ -50,9 +50,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(precision):
+def load_traffic(precision, pairs_per_particle):
     """HBM bytes per force launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source."""
+    if it was taken on the current kernel source and on a bed with the same
+    candidate pairs per particle (within 5 %) as the measured one."""
     p = os.path.join(ROOT, "profiles", "force_kernel_traffic_drum1m.json")
     if not os.path.exists(p):
         return None
@@ -62,15 +63,31 @@ def load_traffic(precision):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
+    pp = d.get("pairs_per_particle")
+    if pp is None or abs(pp - pairs_per_particle) > 0.05 * pairs_per_particle:
+        return None
     e = d.get("per_launch_bytes", {}).get(precision)
     return None if e is None else float(e)
 
 
-def measure(args, precision, scene, label=None, autotune=False, force_block=0, warmup=None,
-            steps=None, keep_state=False):
+def run_steps(sim, n, what, chunk=5000):
+    """Advance sim by n untimed steps in calls of at most `chunk` steps."""
+    done = 0
+    while done < n:
+        k = min(n - done, chunk)
+        sim.step(k)
+        done += k
+        log(f"{what} {done}/{n}")
+
+
+def measure(args, precision, scene, label=None, autotune=False, force_block=0, settle=None,
+            warmup=None, steps=None, keep_state=False, min_touching=None):
+    """Settle `settle` untimed steps (the bed forms its contacts), autotune
+    if asked, run `warmup` untimed steps, then time `steps` steps."""
     import torch
     from paper_2106_09576_amd import Dem
 
+    settle = args.settle if settle is None else settle
     warmup = args.warmup if warmup is None else warmup
     n_steps = args.steps if steps is None else steps
     precision_name = precision
@@ -78,19 +95,22 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0, w
     log(f"{precision}: uploading {scene['particles']['pos'].shape[0]} particles")
     sim = Dem.from_scene(scene, precision=precision_name, force_block=force_block)
     stream = torch.cuda.ExternalStream(sim.stream())
-    log(f"{precision}: warmup {warmup} steps (the bed settles, contacts form)")
-    done = 0
-    while done < warmup:
-        k = min(warmup - done, 5000)
-        sim.step(k)
-        done += k
-        log(f"{precision}: warmup {done}/{warmup}")
+    run_steps(sim, settle, f"{precision}: settling")
     tune = None
     if autotune:
         tune = sim.autotune(trial_steps=args.tune_steps)
         log(f"{precision}: autotuned block {tune['force_block']}, cell factor "
             f"{tune['cell_factor']:.3f}, schedule {tune['rebuild_interval']} "
             f"({tune['steps']} trial steps)")
+    run_steps(sim, warmup, f"{precision}: warmup")
+    st_w = sim.get_stats()
+    if min_touching is not None:
+        c = st_w["n_touching"] / 2 / max(st_w["n_active"], 1)
+        if c < min_touching:
+            sim.close()
+            raise RuntimeError(f"{precision}: only {c:.3f} touching pairs per particle after "
+                               f"{settle} settling and {warmup} warmup steps (need >= "
+                               f"{min_touching}): the bed has not formed its contacts")
     torch.cuda.synchronize()
     st0 = sim.get_stats()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -121,6 +141,8 @@ def measure(args, precision, scene, label=None, autotune=False, force_block=0, w
     achieved = algo_bytes / (force_ms * 1e-3) / 1e9
     res = dict(
         precision=precision_name,
+        settle_steps=settle,
+        warmup_steps=warmup,
         value=n_active * n_steps / wall,
         ms_per_step=1e3 * wall / n_steps,
         event_ms_per_step=ev_ms / n_steps,
@@ -159,18 +181,14 @@ def measure_batched(args, precision):
     n = sum(s["particles"]["pos"].shape[0] for s in scenes)
     log(f"batched {precision}: {len(scenes)} drums, {n} spheres")
     sim = Dem.from_scenes(scenes, precision=precision)
-    done = 0
-    while done < args.batch_warmup:
-        k = min(args.batch_warmup - done, 5000)
-        sim.step(k)
-        done += k
-        log(f"batched {precision}: warmup {done}/{args.batch_warmup}")
+    run_steps(sim, args.batch_settle, f"batched {precision}: settling")
     tune = None
     if not args.no_autotune:
         tune = sim.autotune(trial_steps=args.tune_steps)
         log(f"batched {precision}: autotuned block {tune['force_block']}, cell factor "
             f"{tune['cell_factor']:.3f}, schedule {tune['rebuild_interval']} "
             f"({tune['steps']} trial steps)")
+    run_steps(sim, args.warmup, f"batched {precision}: warmup")
     st0 = sim.get_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -242,11 +260,12 @@ def measure_dam_break(args, precs):
     sc = W.dam_break_scene(n=args.dam_n, t_dam=args.dam_steps * dt, dt=dt)
     sc = dict(sc, config=dict(sc["config"], rebuild_interval=0))
     res = {p: measure(args, p, sc, label=f"{p} dam break", force_block=MAIN_FORCE_BLOCK,
-                      warmup=args.dam_steps, steps=args.dam_steps) for p in precs}
+                      settle=args.dam_steps, steps=args.dam_steps) for p in precs}
     return {"workload": (f"dam break, {args.dam_n} spheres d=1mm in a 0.4 m x 0.2 m box of "
                          f"depth {sc['geometry']['depth']:.3f} m, appendix material, dt=1e-5 s, "
                          f"r_s=1.3 d, dynamic search; the dam is removed after "
-                         f"{args.dam_steps} steps and the next {args.dam_steps} are timed"),
+                         f"{args.dam_steps} steps, {args.warmup} untimed steps follow, "
+                         f"then {args.dam_steps} are timed"),
             "results": res}
 
 
@@ -357,7 +376,9 @@ def cpu_baseline(args, scene, settled, precs):
         dF = np.linalg.norm(Fg - Fo, axis=1)
         dT = np.linalg.norm(Tg - To, axis=1)
         nF, nT = np.linalg.norm(Fo, axis=1), np.linalg.norm(To, axis=1)
-        return {"force_rel_max": float(np.max(dF / (nF + S + 1e-300))),
+        return {"force_normwise": float(np.linalg.norm(dF) / max(np.linalg.norm(nF), 1e-300)),
+                "torque_normwise": float(np.linalg.norm(dT) / max(np.linalg.norm(nT), 1e-300)),
+                "force_rel_max": float(np.max(dF / (nF + S + 1e-300))),
                 "torque_rel_max": float(np.max(dT / (nT + S * R + 1e-300))),
                 "force_rel_max_term_scale": float(np.max(dF / (nF + S2 + 1e-300))),
                 "torque_rel_max_term_scale": float(np.max(dT / (nT + S2 * R + 1e-300))),
@@ -377,7 +398,9 @@ def cpu_baseline(args, scene, settled, precs):
               f"search, {t1 - t0:.1f} s")
     return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle", "sample": sample, "host_cpu": host_cpu(),
-            "gpu_error_vs_oracle": {"steps": steps, "per_particle": "|dF| / (|F| + sum of "
+            "gpu_error_vs_oracle": {"steps": steps, "normwise": "||dF||_2 / ||F||_2 over "
+                                    "the particles' net forces (torques alike)",
+                                    "per_particle": "|dF| / (|F| + sum of "
                                     "contact |F|), torques with lever arm R; *_term_scale: "
                                     "the sum over contacts of the magnitudes of the spring "
                                     "and dashpot terms in place of the contact |F|; after "
@@ -387,8 +410,12 @@ def cpu_baseline(args, scene, settled, precs):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=4000, help="timed steps per leg")
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps right before each timed window (after settling)")
+    ap.add_argument("--settle", type=int, default=20000,
+                    help="untimed settling steps of the drum legs before the warmup: the "
+                         "spheres fall from their lattice and the bed forms its contacts")
     ap.add_argument("--precision", default="both", choices=["fp64", "fp32", "both"])
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--cpu-steps", type=int, default=10)
@@ -410,7 +437,8 @@ def main():
     ap.add_argument("--dam-steps", type=int, default=4000,
                     help="steps with the dam standing, then timed steps after its removal")
     ap.add_argument("--batch-steps", type=int, default=2000)
-    ap.add_argument("--batch-warmup", type=int, default=10000)
+    ap.add_argument("--batch-settle", type=int, default=10000,
+                    help="untimed settling steps of the batch of drums")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 device copies of 1 GiB (read 1 GiB, write 1 GiB each), "
                          "to scale the FETCH_SIZE / WRITE_SIZE counters")
@@ -443,14 +471,15 @@ def main():
     # headline run is reproducible: displacement-triggered search, 64-thread
     # force workgroups, cell edge = r_s
     main_scene = dict(scene, config=dict(scene["config"], rebuild_interval=0))
-    results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK, keep_state=True)
+    results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK, keep_state=True,
+                          min_touching=1.0)
                for p in precs}
     states = {p: results[p].pop("_state") for p in precs}
     settled = states.get("fp64", states[precs[0]])
     copy_gbs = copy_bandwidth()
     main_p = "fp64" if "fp64" in results else precs[0]
     r = results[main_p]
-    traffic = load_traffic(main_p)
+    traffic = load_traffic(main_p, r["pairs_per_particle"])
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -467,12 +496,14 @@ def main():
         "config": {
             "workload": (f"rotating drum, {args.n} spheres d=3mm, R={geo['R']:.4f} m, "
                          f"L={geo['L']:.4f} m, 1 rad/s, dt=5e-6 s, r_s=1.3 d, after "
-                         f"{args.warmup} settling steps; search when a particle may have "
+                         f"{args.settle} settling and {args.warmup} warmup steps; search "
+                         f"when a particle may have "
                          f"moved half the skin, {MAIN_FORCE_BLOCK}-thread force workgroups "
                          f"(the autotuner's choice for this workload)"),
             "n_particles": args.n,
             "pairs_per_particle": round(r["pairs_per_particle"], 3),
             "touching_per_particle": round(r["touching_per_particle"], 3),
+            "settle_steps": args.settle,
         },
         "roofline": {
             "bound": "hbm",
@@ -506,7 +537,8 @@ def main():
         b = {p: measure_batched(args, p) for p in precs}
         res = {"workload": ("256 independent rotating drums in one context, 2k-50k spheres each "
                             "(log-uniform), d=3mm, mu U[0.1,0.5], 0.5-3 rad/s, 35% fill, "
-                            f"dt=5e-6 s, after {args.batch_warmup} settling steps; "
+                            f"dt=5e-6 s, after {args.batch_settle} settling and {args.warmup} "
+                            f"warmup steps; "
                             + ("autotuned block size, cell edge and search schedule"
                                if not args.no_autotune else "search every 20 steps")),
                "results": b}

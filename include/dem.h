@@ -258,12 +258,16 @@ int dem_commit(dem_ctx* ctx);
    calls return DEM_ESTATE until dem_set_particles is called again. */
 int dem_step(dem_ctx* ctx, int64_t n_steps);
 
-/* Current state in input order: positions, velocities, angular velocities
-   (n x 3 each), active flags (n) and time; any pointer may be NULL. */
+/* Current state in input order (Sec. 2.2: the integrated translational and
+   angular state; for velocity Verlet the full-step velocities of Eq. newvv):
+   positions, velocities, angular velocities (n x 3 each), active flags (n;
+   0 once a particle left the domain box, Sec. 3.1) and time; any pointer may
+   be NULL.  Host arrays are caller-owned; DEM_EINVAL for a bad instance,
+   DEM_ESTATE before the particles are set. */
 int dem_get_state(dem_ctx* ctx, int32_t instance, double* pos, double* vel, double* omega,
                   uint8_t* active, double* time_out);
 /* Same into device buffers (caller-owned; written on the library's stream,
-   complete when the call returns). */
+   complete when the call returns).  Same errors. */
 int dem_get_state_device(dem_ctx* ctx, int32_t instance, double* pos, double* vel,
                          double* omega, uint8_t* active);
 
@@ -299,23 +303,36 @@ int dem_restore_mesh_contacts(dem_ctx* ctx, int32_t instance, int64_t n_tri,
                               const int64_t* triples, const double* delta_t);
 
 /* Total contact force and torque on every particle from the last force
-   evaluation of the last dem_step call (zero before the first step). */
+   evaluation of the last dem_step call (zero before the first step): the sum
+   over its contacts of F^n + F^t (Eqs. normal_force, tangential_force after
+   the Coulomb limit of Eqs. coulomb_overlap) and of the tangential and
+   rolling torques (Eq. torque_t and the rolling-model table), walls
+   included, gravity excluded (Sec. 2.1).  n x 3 each, input order,
+   caller-owned host arrays (either may be NULL).  Same errors as
+   dem_get_state. */
 int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque);
 
-/* Candidate particle pairs of the current contact list, each once as
-   (gid_i, gid_j) with gid_i < gid_j, sorted; delta_t = tangential overlap of
-   the pair oriented from i to j (3 per pair); touching = 1 if the spheres
-   overlap at the current positions.  *n_out receives the count; if it
-   exceeds cap nothing else is written and DEM_EINVAL is returned. */
+/* Candidate particle pairs of the current contact list (the fine search of
+   Sec. 3.2: pairs closer than the neighbour threshold at the last search),
+   each once as (gid_i, gid_j) with gid_i < gid_j, sorted; delta_t =
+   tangential overlap of Eq. delta_t of the pair oriented from i to j (3 per
+   pair, zero for pairs that did not touch at the last force evaluation);
+   touching = 1 if the spheres overlap at the current positions (Eq.
+   deltan > 0).  *n_out receives the count; if it exceeds cap nothing else is
+   written and DEM_EINVAL is returned.  Host arrays, caller-owned; any of
+   pairs, delta_t, touching may be NULL. */
 int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                      double* delta_t, uint8_t* touching, int64_t* n_out);
-/* Particle-wall candidates of the analytic walls as (gid, wall_id), sorted,
-   with their tangential overlaps.  Same capacity rule. */
+/* Particle-wall candidates of the analytic walls (Sec. 2.1 last paragraph,
+   walls as bodies of infinite mass and radius) as (gid, wall_id), sorted,
+   with their tangential overlaps (Eq. delta_t).  Same capacity rule and
+   ownership. */
 int dem_get_wall_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                           double* delta_t, int64_t* n_out);
-/* Particle-triangle candidates of the mesh walls as (gid, wall_id,
-   triangle index within the wall) triples, sorted, with the tangential
-   overlap kept in each candidate's slot.  Same capacity rule. */
+/* Particle-triangle candidates of the mesh walls (Sec. 3.7: contacts with
+   boundary faces, lines and points) as (gid, wall_id, triangle index within
+   the wall) triples, sorted, with the tangential overlap (Eq. delta_t) kept
+   in each candidate's slot.  Same capacity rule and ownership. */
 int dem_get_mesh_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* triples,
                           double* delta_t, int64_t* n_out);
 
@@ -324,7 +341,10 @@ int dem_get_mesh_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* 
    for testing the history carry-over and for restarts. */
 int dem_resort(dem_ctx* ctx);
 
-/* Counters of the current state (runs a small reduction on the device). */
+/* Counters of the current state (runs a small reduction on the device):
+   active particles, candidate list entries and touching entries (Sec. 3.2),
+   wall candidates, steps, searches, search geometry (r_s, cell edge, skin,
+   d_max of Sec. 3.2) and device memory.  out is caller-owned. */
 int dem_get_stats(dem_ctx* ctx, dem_stats* out);
 
 /* Stream the library launches on (hipStream_t), for timing with events. */

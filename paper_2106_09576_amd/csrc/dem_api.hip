@@ -458,6 +458,25 @@ int get_chunk_graph(dem_ctx* c, hipGraphExec_t* out) {
   return DEM_OK;
 }
 
+// Capture and instantiate the chunk graphs of all four buffer parities before
+// the first chunk runs, so that no capture or instantiation happens in the
+// middle of a run (the parity a chunk starts with depends on how many
+// searches came before it).
+int prepare_chunk_graphs(dem_ctx* c) {
+  const int save_cur = c->cur, save_pcur = c->pcur;
+  int rc = DEM_OK;
+  for (int a = 0; a < 2 && rc == DEM_OK; ++a)
+    for (int p = 0; p < 2 && rc == DEM_OK; ++p) {
+      c->cur = a;
+      c->pcur = p;
+      hipGraphExec_t g = nullptr;
+      rc = get_chunk_graph(c, &g);
+    }
+  c->cur = save_cur;
+  c->pcur = save_pcur;
+  return rc;
+}
+
 int launch_chunk(dem_ctx* c, int64_t clock_at_start) {
   int rc = set_clock(c, clock_at_start);
   if (rc) return rc;
@@ -535,6 +554,24 @@ int get_dyn_graph(dem_ctx* c, bool search, hipGraphExec_t* out) {
   return DEM_OK;
 }
 
+// The dynamic chunk graphs of all buffer parities, with and without a
+// search at their start, instantiated up front (see prepare_chunk_graphs).
+int prepare_dyn_graphs(dem_ctx* c) {
+  const int save_cur = c->cur, save_pcur = c->pcur;
+  int rc = DEM_OK;
+  for (int a = 0; a < 2 && rc == DEM_OK; ++a)
+    for (int p = 0; p < 2 && rc == DEM_OK; ++p)
+      for (int r = 0; r < 2 && rc == DEM_OK; ++r) {
+        c->cur = a;
+        c->pcur = p;
+        hipGraphExec_t g = nullptr;
+        rc = get_dyn_graph(c, r != 0, &g);
+      }
+  c->cur = save_cur;
+  c->pcur = save_pcur;
+  return rc;
+}
+
 // read back drift records [first, first + count) and fold them into the bound
 int fold_drift(dem_ctx* c, int first, int count) {
   const size_t w0 = (size_t)kDriftSpread * first, nw = (size_t)kDriftSpread * count;
@@ -562,6 +599,7 @@ int step_dynamic(dem_ctx* c, int64_t n_steps) {
   const int64_t s0 = c->step, s_end = s0 + n_steps;
   const bool graphs = !c->timing;
   int rc = DEM_OK;
+  if (graphs && n_steps > kDynChunk && (rc = prepare_dyn_graphs(c))) return rc;
   if (vv) {
     HIPCHK(launch_fill_i32((int*)c->d_drift, 0, 2 * kDriftSpread, c->stream));
     HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
@@ -1652,6 +1690,7 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
   const int64_t K = c->cfg.rebuild_interval;
   const int64_t s0 = c->step, s_end = s0 + n_steps;
   const bool graphs = !c->timing;
+  if (graphs && n_steps >= K && (rc = prepare_chunk_graphs(c))) return rc;
   if (c->cfg.integrator == 0) {
     HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
                              c->F[c->pcur], c->T[c->pcur], nullptr, c->stream));

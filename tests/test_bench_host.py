@@ -22,13 +22,17 @@ def test_more_than_one_gpu_is_refused():
 def test_traffic_comes_from_the_summary_of_the_same_kernel_source(monkeypatch):
     p = os.path.join(ROOT, "profiles", "force_kernel_traffic_drum1m.json")
     d = json.load(open(p))
+    P = d["pairs_per_particle"]
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: d["kernel_source_hash"])
-    assert bench.load_traffic("fp64") == float(d["per_launch_bytes"]["fp64"])
+    assert bench.load_traffic("fp64", P) == float(d["per_launch_bytes"]["fp64"])
     # read + written bytes make up the total
     tot = d["per_launch_read_bytes"]["fp64"] + d["per_launch_write_bytes"]["fp64"]
     assert abs(tot - d["per_launch_bytes"]["fp64"]) <= 1e-6 * tot
+    # a bed with other candidate pairs per particle is not the profiled one
+    assert bench.load_traffic("fp64", 0.8 * P) is None
+    assert bench.load_traffic("fp64", 1.2 * P) is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.load_traffic("fp64") is None
+    assert bench.load_traffic("fp64", P) is None
 
 
 def test_algorithmic_bytes_per_unit():
