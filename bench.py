@@ -363,6 +363,7 @@ def cpu_baseline(args, scene, settled, precs):
     o.step(1)
     t1a = time.perf_counter()
     ref1 = o.forces(), o.term_scale(), o.state()["pos"]
+    cref1 = o.contact_forces()
     t1b = time.perf_counter()
     o.step(steps - 1)
     t1 = time.perf_counter() - (t1b - t1a)
@@ -384,11 +385,26 @@ def cpu_baseline(args, scene, settled, precs):
                 "torque_rel_max_term_scale": float(np.max(dT / (nT + S2 * R + 1e-300))),
                 "pos_abs_max_m": float(np.max(np.abs(xg - xo)))}
 
+    def contact_errors(g):
+        gp, gf = g.get_contact_forces()
+        op, of = cref1
+        if not np.array_equal(gp, op):
+            return {"error": "candidate pairs differ"}
+        nf = np.linalg.norm(of, axis=1)
+        t = nf > 0
+        rel = np.linalg.norm(gf[t] - of[t], axis=1) / nf[t]
+        return {"touching_contacts": int(t.sum()), "max": float(rel.max()),
+                "p999": float(np.quantile(rel, 0.999)), "p99": float(np.quantile(rel, 0.99)),
+                "median": float(np.median(rel))}
+
     err = {}
     for p in precs:
         g = Dem.from_scene(sc, precision=p)
+        g.record_contact_forces(True)
         g.step(1)
         e1 = errors(g, ref1)
+        e1["per_contact"] = contact_errors(g)
+        g.record_contact_forces(False)
         g.step(steps - 1)
         err[p] = dict(errors(g, ref), after_first_step=e1)
         g.close()
@@ -400,6 +416,8 @@ def cpu_baseline(args, scene, settled, precs):
             "kind": "oracle", "sample": sample, "host_cpu": host_cpu(),
             "gpu_error_vs_oracle": {"steps": steps, "normwise": "||dF||_2 / ||F||_2 over "
                                     "the particles' net forces (torques alike)",
+                                    "per_contact": "|dF| / |F| of each touching pair's "
+                                    "F^n + F^t after the first step (max and quantiles)",
                                     "per_particle": "|dF| / (|F| + sum of "
                                     "contact |F|), torques with lever arm R; *_term_scale: "
                                     "the sum over contacts of the magnitudes of the spring "

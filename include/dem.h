@@ -323,6 +323,22 @@ int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque
    pairs, delta_t, touching may be NULL. */
 int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                      double* delta_t, uint8_t* touching, int64_t* n_out);
+/* Per-contact force record, for error measures per contact.  While enabled
+   (enable != 0; off by default), every force evaluation also writes the force
+   F^n + F^t (Eqs. normal_force and tangential_force after the Coulomb limit of
+   Eqs. coulomb_overlap) of each touching pair on the particle whose row holds
+   it, into a device buffer of 24 bytes per neighbour-list entry that the
+   context owns (allocated here or at the next dem_set_particles commit, freed
+   when disabled or destroyed).  DEM_ENOMEM if it cannot be allocated. */
+int dem_record_contact_forces(dem_ctx* ctx, int32_t enable);
+/* The record of the last force evaluation: the candidate pairs of
+   dem_get_contacts in the same order, each with the force on gid_i (3 per
+   pair, zero for a pair that did not touch then).  Same capacity rule and
+   ownership as dem_get_contacts.  DEM_ESTATE when the record is off, or when
+   a constant-interval explicit-Euler run ended with a contact search (the
+   record then belongs to the previous list). */
+int dem_get_contact_forces(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
+                           double* force, int64_t* n_out);
 /* Particle-wall candidates of the analytic walls (Sec. 2.1 last paragraph,
    walls as bodies of infinite mass and radius) as (gid, wall_id), sorted,
    with their tangential overlaps (Eq. delta_t).  Same capacity rule and

@@ -90,6 +90,8 @@ def _load():
                                          C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]
         lib.ora_get_wall_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
                                               C.POINTER(C.c_int64)]
+        lib.ora_get_contact_forces.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                               C.POINTER(C.c_int64)]
         lib.ora_search_params.argtypes = [P, D]
         lib.ora_bruteforce_candidates.argtypes = [P, C.c_int64, C.POINTER(C.c_int64),
                                                   C.POINTER(C.c_int64)]
@@ -280,6 +282,20 @@ class OracleSim:
                                           touch.ctypes.data_as(C.POINTER(C.c_uint8)),
                                           C.byref(nout)), "ora_get_contacts")
         return pairs[:m], dt[:m], touch[:m].astype(bool)
+
+    def contact_forces(self):
+        """Candidate pairs (the order of contacts()) and F^n + F^t on the
+        pair's first particle at the last evaluation (zero if not touching)."""
+        npairs = C.c_int64(); nw = C.c_int64()
+        _check(self._lib.ora_num_contacts(self._h, C.byref(npairs), C.byref(nw)), "num")
+        m = npairs.value
+        pairs = np.empty((max(m, 1), 2), dtype=np.int64)
+        f = np.empty((max(m, 1), 3))
+        nout = C.c_int64()
+        _check(self._lib.ora_get_contact_forces(self._h, max(m, 1),
+                                                pairs.ctypes.data_as(C.POINTER(C.c_int64)),
+                                                _dp(f), C.byref(nout)), "ora_get_contact_forces")
+        return pairs[:m], f[:m]
 
     def wall_contacts(self):
         npairs = C.c_int64(); nw = C.c_int64()

@@ -105,6 +105,7 @@ static ora_wall wall_at(const ora_wall* W, double t) {
 typedef struct {
   int64_t i, j; /* gid_i < gid_j */
   double dt[3]; /* tangential overlap, orientation i -> j */
+  double f[3];  /* F^n + F^t on i at the last evaluation (0 when not touching) */
 } ora_pair;
 
 typedef struct {
@@ -820,6 +821,7 @@ static int build_candidates(ora_sim* s, ora_pair** out, int64_t* nout) {
             P[cnt].i = a < b ? a : b;
             P[cnt].j = a < b ? b : a;
             P[cnt].dt[0] = P[cnt].dt[1] = P[cnt].dt[2] = 0.0;
+            P[cnt].f[0] = P[cnt].f[1] = P[cnt].f[2] = 0.0;
             ++cnt;
           }
         }
@@ -969,6 +971,7 @@ static void compute_forces(ora_sim* s, double t) {
     pp_contact(s, &s->x[3 * i], &s->x[3 * j], &s->v[3 * i], &s->v[3 * j], &s->w[3 * i],
                &s->w[3 * j], s->R[i], s->R[j], s->m[i], s->m[j], s->type[i], s->type[j],
                s->pairs[p].dt, Fi, Mi, Mj, fm);
+    memcpy(s->pairs[p].f, Fi, sizeof(Fi));
     for (int k = 0; k < 3; ++k) {
       s->F[3 * i + k] += Fi[k];
       s->F[3 * j + k] -= Fi[k];
@@ -1430,6 +1433,22 @@ int ora_get_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
       double rsum = s->R[i] + s->R[j];
       touching[p] = vdot(dx, dx) < rsum * rsum;
     }
+  }
+  return ORA_OK;
+}
+
+int ora_get_contact_forces(ora_sim* s, int64_t cap, int64_t* pairs, double* force,
+                           int64_t* n_out) {
+  if (!s || cap < 0) return ORA_EINVAL;
+  if (!s->ready) return ORA_ESTATE;
+  if (n_out) *n_out = s->npairs;
+  if (cap < s->npairs) return ORA_EINVAL;
+  for (int64_t p = 0; p < s->npairs; ++p) {
+    if (pairs) {
+      pairs[2 * p] = s->pairs[p].i;
+      pairs[2 * p + 1] = s->pairs[p].j;
+    }
+    if (force) memcpy(&force[3 * p], s->pairs[p].f, sizeof(double) * 3);
   }
   return ORA_OK;
 }

@@ -94,6 +94,11 @@ int ora_get_term_scale(ora_sim* s, double* scale);
 int ora_num_contacts(ora_sim* s, int64_t* n_pairs, int64_t* n_wall);
 int ora_get_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
                      uint8_t* touching, int64_t* n_out);
+/* per candidate pair (the order of ora_get_contacts): F^n + F^t on the pair's
+   first particle at the last force evaluation, zero for a pair that did not
+   touch then (a record for per-contact error measures; changes nothing) */
+int ora_get_contact_forces(ora_sim* s, int64_t cap, int64_t* pairs, double* force,
+                           int64_t* n_out);
 int ora_get_wall_contacts(ora_sim* s, int64_t cap, int64_t* pairs, double* delta_t,
                           int64_t* n_out);
 /* particle-triangle candidates of mesh walls: (gid, wall id, triangle index

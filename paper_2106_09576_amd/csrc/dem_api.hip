@@ -111,6 +111,9 @@ struct dem_ctx {
   int* mtri[2]{};
   double* mhist[2]{};
   double4 *Fm = nullptr, *Tm = nullptr;
+  // per-contact force record (tests): three planes of cap doubles, or null
+  bool record_pf = false;
+  double* pair_force = nullptr;
   std::vector<int> tri_wall, tri_local;  // per global triangle: instance wall, index in it
   int* nbr[2]{};
   double* hist[2]{};
@@ -226,6 +229,7 @@ void free_particles(dem_ctx* c) {
   c->mtri[0] = c->mtri[1] = nullptr;
   c->mhist[0] = c->mhist[1] = nullptr;
   c->Fm = c->Tm = nullptr;
+  c->pair_force = nullptr;
   c->ready = false;
   c->n = 0;
 }
@@ -342,7 +346,7 @@ int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* dr
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
                       c->d_clock, step_rel, c->d_flags, drift, c->has_mesh ? c->mtri[p] : nullptr,
-                      c->Fm, c->Tm, c->force_block, c->stream));
+                      c->Fm, c->Tm, c->pair_force, c->force_block, c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }
@@ -1120,6 +1124,8 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
   rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
+  if (c->record_pf)
+    rc = rc ? rc : dalloc_t(c, &c->pair_force, (size_t)std::max<int64_t>(c->cap, 1) * 3);
   if (!htri.empty()) {
     rc = rc ? rc : dalloc_t(c, &c->d_tri, htri.size());
     rc = rc ? rc : dalloc_t(c, &c->d_mcell, hcell.size());
@@ -2057,6 +2063,95 @@ int dem_restore_mesh_contacts(dem_ctx* c, int32_t instance, int64_t n_tri,
     HIPCHK(hipMemcpyAsync(c->mhist[L], th.data(), th.size() * sizeof(double),
                           hipMemcpyHostToDevice, c->stream));
   return finish(c);
+}
+
+int dem_record_contact_forces(dem_ctx* c, int32_t enable) {
+  if (!c) return set_err(DEM_EINVAL, "null context");
+  if (int rc = wait_user(c)) return rc;
+  const bool on = enable != 0;
+  if (on == c->record_pf) return DEM_OK;
+  destroy_graphs(c);  // the captured force launches hold the record's address
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->record_pf = on;
+  if (!c->ready) return DEM_OK;
+  if (!on) {
+    dfree(c, c->pair_force);
+    c->pair_force = nullptr;
+    return DEM_OK;
+  }
+  const size_t m = (size_t)std::max<int64_t>(c->cap, 1) * 3;
+  if (int rc = dalloc_t(c, &c->pair_force, m)) {
+    c->record_pf = false;
+    return rc;
+  }
+  HIPCHK(launch_fill_i32((int*)c->pair_force, 0, (int64_t)m * 2, c->stream));
+  return finish(c);
+}
+
+int dem_get_contact_forces(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
+                           double* force, int64_t* n_out) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
+  if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
+  if (!c->pair_force)
+    return set_err(DEM_ESTATE, "call dem_record_contact_forces(ctx, 1) before dem_step");
+  if (c->cfg.integrator == 1 && c->cfg.rebuild_interval > 0 &&
+      c->step % c->cfg.rebuild_interval == 0 && c->step > 0)
+    return set_err(DEM_ESTATE,
+                   "the last step ended with a contact search (explicit Euler): the record "
+                   "belongs to the previous contact list");
+  if (int rc = wait_user(c)) return rc;
+  HostSnapshot h;
+  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> rl(n), nb((size_t)c->cap);
+  std::vector<double> pf((size_t)c->cap * 3);
+  const int L = c->pcur;
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(rl.data(), c->rowlen[L], n * sizeof(int), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(nb.data(), c->nbr[L], (size_t)c->cap * sizeof(int),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(pf.data(), c->pair_force, (size_t)c->cap * 3 * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  }
+  if (int rc = finish(c)) return rc;
+  struct Rec {
+    int64_t i, j;
+    double f[3];
+  };
+  std::vector<Rec> out;
+  const int64_t base = c->inst[(size_t)instance].p_begin;
+  for (size_t p = 0; p < n; ++p) {
+    if ((h.info[p] >> kInstShift) != instance) continue;
+    for (int k = 0; k < rl[p]; ++k) {
+      const int64_t e = nbr_entry((int)p, k, c->max_nb);
+      const int jr = nb[(size_t)e];
+      const int q = jr & 0x7fffffff;
+      if (h.gid[p] >= h.gid[q]) continue;
+      // bit 31: the pair touched at the last evaluation, which wrote its force
+      const bool t = (jr & (int)0x80000000u) != 0;
+      Rec r;
+      r.i = h.gid[p] - base;
+      r.j = h.gid[q] - base;
+      for (int a = 0; a < 3; ++a) r.f[a] = t ? pf[(size_t)a * (size_t)c->cap + (size_t)e] : 0.0;
+      out.push_back(r);
+    }
+  }
+  std::sort(out.begin(), out.end(),
+            [](const Rec& a, const Rec& b) { return a.i != b.i ? a.i < b.i : a.j < b.j; });
+  if (n_out) *n_out = (int64_t)out.size();
+  if ((int64_t)out.size() > cap)
+    return set_err(DEM_EINVAL, "cap %lld < %zu pairs", (long long)cap, out.size());
+  for (size_t m = 0; m < out.size(); ++m) {
+    if (pairs) {
+      pairs[2 * m] = out[m].i;
+      pairs[2 * m + 1] = out[m].j;
+    }
+    if (force)
+      for (int a = 0; a < 3; ++a) force[3 * m + a] = out[m].f[a];
+  }
+  return DEM_OK;
 }
 
 int dem_get_wall_contacts(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,

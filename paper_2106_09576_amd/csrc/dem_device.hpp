@@ -199,14 +199,17 @@ hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double
 // Euler (forces at the current state, then the update; forces stored).
 // xsel (may be null): particles i with xsel[i] >= 0 add the force and torque
 // Fx[i] / Tx[i] to their contact sums (the mesh contacts of the same state;
-// xsel is the first mesh candidate slot).
+// xsel is the first mesh candidate slot).  pf (may be null): the force of
+// every touching pair on the row's particle is also written to entry (i, k)
+// of three planes of l.cap doubles (a per-contact record for tests).
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
                         const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
                         ParticleBufs out, const int* info, NbrList l, WallSlots ws,
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
                         const int* flags, unsigned long long* drift, const int* xsel,
-                        const double4* Fx, const double4* Tx, int block, hipStream_t s);
+                        const double4* Fx, const double4* Tx, double* pf, int block,
+                        hipStream_t s);
 // Contacts of the particles with triangle candidates at time (*clock +
 // step_rel) dt (tangential overlaps updated): their force and torque into
 // Fm / Tm (written for those particles only).

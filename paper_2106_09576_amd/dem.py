@@ -102,6 +102,8 @@ SIGNATURES = {
     "dem_get_forces": (C.c_int, [P, C.c_int32, DP, DP]),
     "dem_get_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, U8P, I64P]),
     "dem_get_wall_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
+    "dem_record_contact_forces": (C.c_int, [P, C.c_int32]),
+    "dem_get_contact_forces": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_add_mesh_wall": (C.c_int, [P, C.c_int32, C.c_int64, DP, C.c_int64, I32P, C.c_int32, DP,
                                     DP, C.c_double, C.c_double, I32P]),
     "dem_get_mesh_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
@@ -307,6 +309,24 @@ class Dem:
         self._check(self._lib.dem_get_contacts(self._h, instance, max(m, 1), pairs.ctypes.data_as(I64P),
                                                _d(dt), touch.ctypes.data_as(U8P), C.byref(cnt)))
         return pairs[:m], dt[:m], touch[:m].astype(bool)
+
+    def record_contact_forces(self, enable=True):
+        self._check(self._lib.dem_record_contact_forces(self._h, 1 if enable else 0))
+
+    def get_contact_forces(self, instance=0):
+        """Candidate pairs (the order of get_contacts) and the force of the
+        last evaluation on each pair's first particle (zero if not touching)."""
+        cnt = C.c_int64()
+        rc = self._lib.dem_get_contact_forces(self._h, instance, 0, None, None, C.byref(cnt))
+        if rc not in (DEM_OK, DEM_EINVAL):
+            self._check(rc)
+        m = cnt.value
+        pairs = np.empty((max(m, 1), 2), dtype=np.int64)
+        f = np.empty((max(m, 1), 3))
+        self._check(self._lib.dem_get_contact_forces(self._h, instance, max(m, 1),
+                                                     pairs.ctypes.data_as(I64P), _d(f),
+                                                     C.byref(cnt)))
+        return pairs[:m], f[:m]
 
     def get_wall_contacts(self, instance=0):
         cnt = C.c_int64()

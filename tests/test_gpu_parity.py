@@ -56,6 +56,26 @@ def force_err(g, o):
     return ef, et
 
 
+def contact_force_errors(g, o):
+    """The per-contact and normwise error measures of the FP32 law: over the
+    pairs touching at the last evaluation, |dF| / |F| of each contact's
+    F^n + F^t (max and 99.9th percentile), and ||dF||_2 / ||F||_2 over the
+    particles' net contact forces.  Needs g.record_contact_forces(True)
+    before the step."""
+    gp, gf = g.get_contact_forces()
+    op, of = o.contact_forces()
+    assert np.array_equal(gp, op)
+    nf = np.linalg.norm(of, axis=1)
+    t = nf > 0
+    assert np.array_equal(np.linalg.norm(gf, axis=1) > 0, t)  # same touching pairs
+    rel = np.linalg.norm(gf[t] - of[t], axis=1) / nf[t]
+    Fg, _ = g.get_forces()
+    Fo, _, _ = o.forces()
+    nw = np.linalg.norm(Fg - Fo) / max(np.linalg.norm(Fo), 1e-300)
+    return {"contacts": int(t.sum()), "max": float(rel.max()) if t.any() else 0.0,
+            "p999": float(np.quantile(rel, 0.999)) if t.any() else 0.0, "normwise": float(nw)}
+
+
 def make(Dem, scene, precision="fp64"):
     g, o = both(Dem, scene, precision)
     o.radius = scene["particles"]["radius"]
@@ -98,11 +118,16 @@ def test_contact_sets_and_history_after_steps(Dem):
 def test_forces_one_step(Dem, precision, tol):
     sc = W.dense_snapshot(n=3000, seed=21, polydisperse=0.2, n_types=2)
     g, o = make(Dem, sc, precision)
+    g.record_contact_forces(True)
     g.step(1)
     o.step(1)
     ef, et = force_err(g, o)
-    print(precision, "force err", ef, "torque err", et, flush=True)
+    ce = contact_force_errors(g, o)
+    print(precision, "force err", ef, "torque err", et, "per contact", ce, flush=True)
     assert ef <= tol and et <= tol
+    assert ce["contacts"] > 1000
+    assert ce["normwise"] <= tol and ce["p999"] <= tol
+    assert ce["max"] <= (1e-10 if precision == "fp64" else 1e-4)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", FP32_TOL)])
@@ -379,10 +404,18 @@ def test_drum_1m_settled_forces_one_step_both_precisions(Dem):
     nF, nT = np.linalg.norm(Fo, axis=1), np.linalg.norm(To, axis=1)
     for precision in ("fp64", "fp32"):
         gp = Dem.from_scene(snap, precision=precision)
+        gp.record_contact_forces(True)
         gp.step(1)
         if precision == "fp64":
             (gd, od), _ = assert_same_contacts(gp, o)
             assert len(gd) > 4_000_000
+        ce = contact_force_errors(gp, o)
+        print("settled drum", precision, "per contact", ce, flush=True)
+        assert ce["contacts"] > 1_000_000
+        if precision == "fp64":
+            assert ce["normwise"] <= 1e-12 and ce["max"] <= 1e-9
+        else:
+            assert ce["normwise"] <= 1e-5 and ce["p999"] <= 1e-5
         Fg, Tg = gp.get_forces()
         gp.close()
         dF = np.linalg.norm(Fg - Fo, axis=1)
