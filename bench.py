@@ -283,6 +283,44 @@ def measure_variants(args, base_scene):
                         "and with the viscous rolling torque, FP64 law", "results": out}
 
 
+def measure_silos(args, precs):
+    """The two silo workloads: the wedge silo of 200,000 spheres (d uniform in
+    [2, 3] mm, 30 degree wedge to a 12 mm slot, dt = 5e-6 s) and the
+    cylindrical silo of 4.3M spheres (log-normal d, 60 degree cone to a 40 mm
+    outlet, E = 1e7 Pa, dt = 2e-6 s).  The spheres start at rest on a lattice
+    above the plugged outlet and fall into a bed (untimed fill); the plug
+    switches off at the end of the fill, and after the warmup steps the
+    discharge is timed (spheres leaving the domain below the outlet become
+    inactive; the rate counts active particle-steps).  Dynamic search,
+    64-thread force workgroups."""
+    import workloads as W
+    out = {}
+    legs = (("wedge_silo", args.silo_fill, args.silo_steps,
+             lambda t_open: W.wedge_silo_scene(t_open=t_open), 5.0e-6),
+            ("hopper_silo", args.hopper_fill, args.hopper_steps,
+             lambda t_open: W.hopper_silo_scene(t_open=t_open), 2.0e-6))
+    for name, fill, steps, make, dt in legs:
+        log(f"{name}: building the scene")
+        sc = make(fill * dt)
+        sc = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+        res = {}
+        for p in precs:
+            r = measure(args, p, sc, label=f"{p} {name}", force_block=MAIN_FORCE_BLOCK,
+                        settle=fill, steps=steps)
+            r["force_kernel_frac_of_peak"] = r["force_kernel_gbs"] / HBM_PEAK_GBS
+            res[p] = r
+        g = sc["geometry"]
+        out[name] = {"workload": (f"{name.replace('_', ' ')}, {sc['particles']['pos'].shape[0]} "
+                                  f"spheres, geometry {g}, dt={dt:g} s, r_s=1.3 d_max, "
+                                  f"dynamic search; fill of {fill} steps with the outlet "
+                                  f"plugged, the plug off at its end, {args.warmup} warmup "
+                                  f"steps, then {steps} discharge steps timed"),
+                     "results": res}
+        if "fp32" in res and "fp64" in res:
+            out[name]["fp32_vs_fp64"] = res["fp32"]["value"] / res["fp64"]["value"]
+    return out
+
+
 def measure_meshed_drum(args):
     """The headline drum with its cylinder as a spinning triangle mesh of
     192 x 48 squares (18,432 triangles): particle-face/edge/vertex contacts
@@ -409,11 +447,28 @@ def cpu_baseline(args, scene, settled, precs):
         err[p] = dict(errors(g, ref), after_first_step=e1)
         g.close()
     log(f"cpu baseline: {n * steps / (t1 - t0):.3g} particle-steps/s; GPU vs oracle {err}")
+    # the OpenMP timing build of the same oracle on all usable host cores
+    all_cores = None
+    try:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or host_cpu()["cpus_usable"]
+        op = oracle_from_scene(sc, parallel=True)
+        tp0 = time.perf_counter()
+        op.step(steps)
+        tp1 = time.perf_counter()
+        all_cores = {"value": n * steps / (tp1 - tp0), "unit": "particle-steps/s",
+                     "threads": threads,
+                     "sample": f"the same {steps} steps with the oracle's OpenMP timing build "
+                               f"(pair laws in parallel, per-particle sums in a fixed order), "
+                               f"{tp1 - tp0:.2f} s"}
+        log(f"cpu baseline, {threads} threads: {all_cores['value']:.3g} particle-steps/s")
+    except Exception as e:  # noqa: BLE001 (the 1-thread figure stands on its own)
+        all_cores = {"error": str(e)}
     sample = (f"FP64 oracle, 1 thread, the 1M-sphere drum from the settled state of the FP64 "
               f"headline leg (tangential overlaps zero), steps 1-{steps} after the initial "
               f"search, {t1 - t0:.1f} s")
     return {"value": n * steps / (t1 - t0), "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle", "sample": sample, "host_cpu": host_cpu(),
+            "all_cores": all_cores,
             "gpu_error_vs_oracle": {"steps": steps, "normwise": "||dF||_2 / ||F||_2 over "
                                     "the particles' net forces (torques alike)",
                                     "per_contact": "|dF| / |F| of each touching pair's "
@@ -451,6 +506,15 @@ def main():
     ap.add_argument("--skip-variants", action="store_true",
                     help="skip the drum legs with the linear law and viscous rolling")
     ap.add_argument("--skip-mesh", action="store_true", help="skip the meshed-drum leg")
+    ap.add_argument("--skip-silos", action="store_true", help="skip the two silo legs")
+    ap.add_argument("--silo-fill", type=int, default=20000,
+                    help="fill steps of the wedge silo before its outlet opens")
+    ap.add_argument("--silo-steps", type=int, default=4000,
+                    help="timed discharge steps of the wedge silo")
+    ap.add_argument("--hopper-fill", type=int, default=10000,
+                    help="fill steps of the 4.3M-sphere silo before its outlet opens")
+    ap.add_argument("--hopper-steps", type=int, default=1000,
+                    help="timed discharge steps of the 4.3M-sphere silo")
     ap.add_argument("--dam-n", type=int, default=1_280_000)
     ap.add_argument("--dam-steps", type=int, default=4000,
                     help="steps with the dam standing, then timed steps after its removal")
@@ -571,6 +635,7 @@ def main():
             ("batched", not args.skip_batched, batched),
             ("model_variants", not args.skip_variants, lambda: measure_variants(args, scene)),
             ("meshed_drum", not args.skip_mesh, lambda: measure_meshed_drum(args)),
+            ("silos", not args.skip_silos, lambda: measure_silos(args, precs)),
             ("dam_break", not args.skip_dam, lambda: measure_dam_break(args, precs)),
             ("small_box", not args.skip_small, lambda: measure_small_box(args)),
             ("cpu_baseline", not args.skip_cpu,

@@ -323,6 +323,19 @@ int dem_get_forces(dem_ctx* ctx, int32_t instance, double* force, double* torque
    pairs, delta_t, touching may be NULL. */
 int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                      double* delta_t, uint8_t* touching, int64_t* n_out);
+/* The candidate pairs of dem_get_contacts written to device buffers
+   (caller-owned, on the device of the context; written on the library's
+   stream, complete when the call returns): pairs (2 int64 per pair, gid_i <
+   gid_j), delta_t (3 doubles per pair), touching (1 byte per pair); any of
+   them may be NULL.  Same pairs and values as dem_get_contacts, but in the
+   library's spatial order (the sorted order of gid_i, then the order of its
+   neighbour row) instead of gid order.  *n_out (host) receives the count; if
+   it exceeds cap nothing else is written and DEM_EINVAL is returned.  Uses a
+   device workspace of about 8 bytes per 256 particles, allocated and freed
+   by the call (DEM_EHIP if that fails); DEM_EINVAL when the neighbour list
+   has 2^31 entries or more. */
+int dem_get_contacts_device(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
+                            double* delta_t, uint8_t* touching, int64_t* n_out);
 /* Per-contact force record, for error measures per contact.  While enabled
    (enable != 0; off by default), every force evaluation also writes the force
    F^n + F^t (Eqs. normal_force and tangential_force after the Coulomb limit of

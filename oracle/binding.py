@@ -15,6 +15,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle_dem.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# timing build for the benchmark's CPU baseline: the same source with the
+# pair loop, kicks and drifts spread over OpenMP threads (deterministic
+# per-particle sums); the tests use the serial library only
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 ORA_ERRORS = {-1: "EINVAL", -3: "ENOMEM", -5: "EUNSTABLE", -6: "ESTATE"}
 
@@ -24,13 +28,17 @@ def oracle_lib_path() -> str:
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, FP64, no contraction)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain C99, FP64, no contraction), and its
+    OpenMP timing build."""
+    builds = ((_LIB, ["-O2"]),
+              (_LIB_OMP, ["-O3", "-march=x86-64-v2", "-fopenmp", "-DORA_PARALLEL"]))
+    for lib, extra in builds:
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            cmd = ["gcc", "-std=c99", *extra, "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                   "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+            subprocess.run(cmd, check=True)
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -50,56 +58,67 @@ class _Material(C.Structure):
 
 
 _lib = None
+_lib_omp = None
 
 
-def _load():
-    global _lib
+def _load(parallel=False):
+    global _lib, _lib_omp
+    if parallel:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP):
+                build_oracle()
+            _lib_omp = _declare(C.CDLL(_LIB_OMP))
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB):
             build_oracle()
-        lib = C.CDLL(_LIB)
-        P = C.c_void_p
-        D = C.POINTER(C.c_double)
-        lib.ora_create.argtypes = [C.POINTER(_Config), C.POINTER(P)]
-        lib.ora_destroy.argtypes = [P]
-        lib.ora_destroy.restype = None
-        lib.ora_set_material.argtypes = [P, C.c_int32, C.POINTER(_Material)]
-        lib.ora_set_particles.argtypes = [P, C.c_int64, D, D, D, D, C.POINTER(C.c_int32)]
-        lib.ora_add_plane.argtypes = [P, D, D, D, C.c_int32, D, D, C.c_double, C.c_double,
-                                      C.POINTER(C.c_int32)]
-        lib.ora_add_cylinder.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double,
-                                         C.c_int32, C.c_int32, C.c_double, C.c_double,
-                                         C.c_double, C.POINTER(C.c_int32)]
-        lib.ora_add_cone.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
-                                     C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
-                                     C.POINTER(C.c_int32)]
-        lib.ora_add_mesh.argtypes = [P, C.c_int64, D, C.c_int64, C.POINTER(C.c_int32),
-                                     C.c_int32, D, D, C.c_double, C.c_double,
-                                     C.POINTER(C.c_int32)]
-        lib.ora_get_mesh_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
-                                              C.POINTER(C.c_int64)]
-        lib.ora_triangle_closest.argtypes = [D, D, D]
-        lib.ora_step.argtypes = [P, C.c_int64]
-        lib.ora_set_wall_velocity.argtypes = [P, C.c_int32, D]
-        lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
-        lib.ora_get_forces.argtypes = [P, D, D]
-        lib.ora_get_force_scale.argtypes = [P, D]
-        lib.ora_get_term_scale.argtypes = [P, D]
-        lib.ora_num_contacts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
-        lib.ora_get_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
-                                         C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]
-        lib.ora_get_wall_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
-                                              C.POINTER(C.c_int64)]
-        lib.ora_get_contact_forces.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
-                                               C.POINTER(C.c_int64)]
-        lib.ora_search_params.argtypes = [P, D]
-        lib.ora_bruteforce_candidates.argtypes = [P, C.c_int64, C.POINTER(C.c_int64),
-                                                  C.POINTER(C.c_int64)]
-        lib.ora_pair_force.argtypes = [P, D, D, D, D, D, D, C.c_double, C.c_double,
-                                       C.c_int32, C.c_int32, D, D, D, D,
-                                       C.POINTER(C.c_int32)]
-        _lib = lib
+        _lib = _declare(C.CDLL(_LIB))
     return _lib
+
+
+def _declare(lib):
+    """Argument types of the oracle's C interface."""
+    P = C.c_void_p
+    D = C.POINTER(C.c_double)
+    lib.ora_create.argtypes = [C.POINTER(_Config), C.POINTER(P)]
+    lib.ora_destroy.argtypes = [P]
+    lib.ora_destroy.restype = None
+    lib.ora_set_material.argtypes = [P, C.c_int32, C.POINTER(_Material)]
+    lib.ora_set_particles.argtypes = [P, C.c_int64, D, D, D, D, C.POINTER(C.c_int32)]
+    lib.ora_add_plane.argtypes = [P, D, D, D, C.c_int32, D, D, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int32)]
+    lib.ora_add_cylinder.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double,
+                                     C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                     C.c_double, C.POINTER(C.c_int32)]
+    lib.ora_add_cone.argtypes = [P, D, D, C.c_double, C.c_double, C.c_double, C.c_double,
+                                 C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                 C.POINTER(C.c_int32)]
+    lib.ora_add_mesh.argtypes = [P, C.c_int64, D, C.c_int64, C.POINTER(C.c_int32),
+                                 C.c_int32, D, D, C.c_double, C.c_double,
+                                 C.POINTER(C.c_int32)]
+    lib.ora_get_mesh_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                          C.POINTER(C.c_int64)]
+    lib.ora_triangle_closest.argtypes = [D, D, D]
+    lib.ora_step.argtypes = [P, C.c_int64]
+    lib.ora_set_wall_velocity.argtypes = [P, C.c_int32, D]
+    lib.ora_get_state.argtypes = [P, D, D, D, C.POINTER(C.c_uint8), D]
+    lib.ora_get_forces.argtypes = [P, D, D]
+    lib.ora_get_force_scale.argtypes = [P, D]
+    lib.ora_get_term_scale.argtypes = [P, D]
+    lib.ora_num_contacts.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.ora_get_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                     C.POINTER(C.c_uint8), C.POINTER(C.c_int64)]
+    lib.ora_get_wall_contacts.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                          C.POINTER(C.c_int64)]
+    lib.ora_get_contact_forces.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), D,
+                                           C.POINTER(C.c_int64)]
+    lib.ora_search_params.argtypes = [P, D]
+    lib.ora_bruteforce_candidates.argtypes = [P, C.c_int64, C.POINTER(C.c_int64),
+                                              C.POINTER(C.c_int64)]
+    lib.ora_pair_force.argtypes = [P, D, D, D, D, D, D, C.c_double, C.c_double,
+                                   C.c_int32, C.c_int32, D, D, D, D,
+                                   C.POINTER(C.c_int32)]
+    return lib
 
 
 def _dp(a):
@@ -130,8 +149,8 @@ class OracleSim:
     def __init__(self, dt, gravity=(0.0, 0.0, -9.81), domain_lo=(0, 0, 0),
                  domain_hi=(1, 1, 1), neighbor_threshold=1.3, cell_factor=None,
                  rebuild_interval=20, integrator="verlet", rolling_model="constant",
-                 contact_model="nonlinear", characteristic_velocity=0.0):
-        lib = _load()
+                 contact_model="nonlinear", characteristic_velocity=0.0, parallel=False):
+        lib = _load(parallel)
         cfg = _Config()
         cfg.dt = dt
         cfg.gravity = (C.c_double * 3)(*gravity)
@@ -349,15 +368,17 @@ def triangle_closest(corners, x):
     return feat, out[1], out[2], out[3:6].copy()
 
 
-def oracle_from_scene(scene: dict) -> OracleSim:
-    """Build an oracle simulation from a scene dictionary (see ``workloads``)."""
+def oracle_from_scene(scene: dict, parallel: bool = False) -> OracleSim:
+    """Build an oracle simulation from a scene dictionary (see ``workloads``);
+    parallel=True uses the OpenMP timing build."""
     c = scene["config"]
     sim = OracleSim(dt=c["dt"], gravity=c["gravity"], domain_lo=c["domain_lo"],
                     domain_hi=c["domain_hi"], neighbor_threshold=c["neighbor_threshold"],
                     cell_factor=c["cell_factor"], rebuild_interval=c["rebuild_interval"],
                     integrator=c["integrator"], rolling_model=c["rolling_model"],
                     contact_model=c.get("contact_model", "nonlinear"),
-                    characteristic_velocity=c.get("characteristic_velocity", 0.0))
+                    characteristic_velocity=c.get("characteristic_velocity", 0.0),
+                    parallel=parallel)
     for t, m in enumerate(scene["materials"]):
         sim.set_material(t, m["density"], m["youngs"], m["poisson"], m["restitution"],
                          m["friction"], m["rolling_friction"])

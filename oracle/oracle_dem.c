@@ -144,6 +144,14 @@ struct ora_sim {
   int64_t nmpairs;
   int64_t step;
   int ready;
+#ifdef ORA_PARALLEL
+  /* timing build only: per-pair law results and the per-particle pair index */
+  double* prec;           /* 11 doubles per pair: F_i, M_i, M_j, the two scales */
+  int64_t prec_cap;
+  int64_t *ifirst, *jfirst, *jlist;
+  int64_t idx_n, idx_pairs;
+  int idx_dirty;
+#endif
 };
 
 /* ------------------------------------------------------------------ vectors */
@@ -875,6 +883,9 @@ static int rebuild(ora_sim* s) {
   free(s->pairs);
   s->pairs = np;
   s->npairs = nn;
+#ifdef ORA_PARALLEL
+  s->idx_dirty = 1;
+#endif
 
   /* particle-wall candidates, in (gid, wall id) order */
   int64_t cap = 64, cnt = 0;
@@ -959,13 +970,96 @@ static int rebuild(ora_sim* s) {
 
 /* ------------------------------------------------------------------ forces */
 
+#ifdef ORA_PARALLEL
+/* Timing build (benchmark CPU baseline, not the parity oracle): the law of
+   every pair runs in parallel into a per-pair record, then every particle
+   sums its records, first those where it is the pair's first particle, then
+   those where it is the second, each in list order.  That order does not
+   depend on the number of threads, so the result is deterministic; it
+   differs from the serial oracle's by summation order only. */
+static int par_index(ora_sim* s) {
+  const int64_t n = s->n, np = s->npairs;
+  if (!s->idx_dirty && s->idx_n == n && s->idx_pairs == np) return ORA_OK;
+  free(s->ifirst);
+  free(s->jfirst);
+  free(s->jlist);
+  s->ifirst = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  s->jfirst = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  s->jlist = (int64_t*)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+  if (!s->ifirst || !s->jfirst || !s->jlist) return ORA_ENOMEM;
+  for (int64_t p = 0; p < np; ++p) {
+    s->ifirst[s->pairs[p].i + 1] += 1;
+    s->jfirst[s->pairs[p].j + 1] += 1;
+  }
+  for (int64_t q = 0; q < n; ++q) {
+    s->ifirst[q + 1] += s->ifirst[q];
+    s->jfirst[q + 1] += s->jfirst[q];
+  }
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  if (!fill) return ORA_ENOMEM;
+  memcpy(fill, s->jfirst, sizeof(int64_t) * (size_t)n);
+  for (int64_t p = 0; p < np; ++p) s->jlist[fill[s->pairs[p].j]++] = p;
+  free(fill);
+  if (s->prec_cap < np) {
+    free(s->prec);
+    s->prec = (double*)malloc(sizeof(double) * 11 * (size_t)np);
+    if (!s->prec) return ORA_ENOMEM;
+    s->prec_cap = np;
+  }
+  s->idx_n = n;
+  s->idx_pairs = np;
+  s->idx_dirty = 0;
+  return ORA_OK;
+}
+
+static void par_pair_forces(ora_sim* s) {
+  const int64_t np = s->npairs, n = s->n;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < np; ++p) {
+    int64_t i = s->pairs[p].i, j = s->pairs[p].j;
+    double* r = &s->prec[11 * p];
+    pp_contact(s, &s->x[3 * i], &s->x[3 * j], &s->v[3 * i], &s->v[3 * j], &s->w[3 * i],
+               &s->w[3 * j], s->R[i], s->R[j], s->m[i], s->m[j], s->type[i], s->type[j],
+               s->pairs[p].dt, r, r + 3, r + 6, r + 9);
+    memcpy(s->pairs[p].f, r, sizeof(double) * 3);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < n; ++q) {
+    for (int64_t p = s->ifirst[q]; p < s->ifirst[q + 1]; ++p) {
+      const double* r = &s->prec[11 * p];
+      for (int k = 0; k < 3; ++k) {
+        s->F[3 * q + k] += r[k];
+        s->T[3 * q + k] += r[3 + k];
+      }
+      s->S[q] += r[9];
+      s->S2[q] += r[10];
+    }
+    for (int64_t m = s->jfirst[q]; m < s->jfirst[q + 1]; ++m) {
+      const double* r = &s->prec[11 * s->jlist[m]];
+      for (int k = 0; k < 3; ++k) {
+        s->F[3 * q + k] -= r[k];
+        s->T[3 * q + k] += r[6 + k];
+      }
+      s->S[q] += r[9];
+      s->S2[q] += r[10];
+    }
+  }
+}
+#endif
+
 static void compute_forces(ora_sim* s, double t) {
   size_t n3 = 3 * (size_t)s->n;
   memset(s->F, 0, sizeof(double) * n3);
   memset(s->T, 0, sizeof(double) * n3);
   memset(s->S, 0, sizeof(double) * (size_t)s->n);
   memset(s->S2, 0, sizeof(double) * (size_t)s->n);
+#ifdef ORA_PARALLEL
+  const int64_t serial_pairs = par_index(s) == ORA_OK ? 0 : s->npairs;
+  if (serial_pairs == 0) par_pair_forces(s);
+  for (int64_t p = 0; p < serial_pairs; ++p) {
+#else
   for (int64_t p = 0; p < s->npairs; ++p) {
+#endif
     int64_t i = s->pairs[p].i, j = s->pairs[p].j;
     double Fi[3], Mi[3], Mj[3], fm[2];
     pp_contact(s, &s->x[3 * i], &s->x[3 * j], &s->v[3 * i], &s->v[3 * j], &s->w[3 * i],
@@ -1009,6 +1103,9 @@ static void compute_forces(ora_sim* s, double t) {
 /* ------------------------------------------------------------------- steps */
 
 static void kick(ora_sim* s, double h) {
+#ifdef ORA_PARALLEL
+#pragma omp parallel for schedule(static)
+#endif
   for (int64_t i = 0; i < s->n; ++i) {
     if (!s->active[i]) continue;
     for (int k = 0; k < 3; ++k) {
@@ -1020,6 +1117,9 @@ static void kick(ora_sim* s, double h) {
 }
 
 static void drift(ora_sim* s, double dt) {
+#ifdef ORA_PARALLEL
+#pragma omp parallel for schedule(static)
+#endif
   for (int64_t i = 0; i < s->n; ++i) {
     if (!s->active[i]) continue;
     for (int k = 0; k < 3; ++k) s->x[3 * i + k] = s->x[3 * i + k] + s->v[3 * i + k] * dt;
@@ -1089,6 +1189,12 @@ static void free_particles(ora_sim* s) {
   s->x = s->v = s->w = s->R = s->m = s->I = s->F = s->T = s->S = s->S2 = s->xref = NULL;
   s->type = NULL; s->active = NULL; s->pairs = NULL; s->wpairs = NULL; s->mpairs = NULL;
   s->npairs = s->nwpairs = s->nmpairs = 0;
+#ifdef ORA_PARALLEL
+  free(s->prec); free(s->ifirst); free(s->jfirst); free(s->jlist);
+  s->prec = NULL; s->ifirst = s->jfirst = s->jlist = NULL;
+  s->prec_cap = 0;
+  s->idx_dirty = 1;
+#endif
 }
 
 void ora_destroy(ora_sim* s) {

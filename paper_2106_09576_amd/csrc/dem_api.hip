@@ -2065,6 +2065,57 @@ int dem_restore_mesh_contacts(dem_ctx* c, int32_t instance, int64_t n_tri,
   return finish(c);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Candidate pairs of an instance into caller device buffers; scratch is
+// device memory of at least pairs_scratch_ints(c->n) ints.
+int contacts_device(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
+                    double* delta_t, uint8_t* touching, int64_t* n_out, int* scratch) {
+  const int L = c->pcur;
+  const int64_t nb = (c->n + kBlock - 1) / kBlock;
+  HIPCHK(launch_pairs_count(c->sp, instance, c->info[L], c->gid[L], nlist(c, L), scratch,
+                            c->stream));
+  int total = 0;
+  HIPCHK(hipMemcpyAsync(&total, scratch + 2 * nb, sizeof(int), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (n_out) *n_out = total;
+  if (total > cap)
+    return set_err(DEM_EINVAL, "cap %lld < %d contacts", (long long)cap, total);
+  HIPCHK(launch_pairs_fill(c->sp, instance, (int)c->inst[(size_t)instance].p_begin,
+                           c->pos[c->cur], c->info[L], c->gid[L], nlist(c, L), scratch, pairs,
+                           delta_t, touching, c->stream));
+  return finish(c);
+}
+
+int contacts_device_check(dem_ctx* c, int32_t instance, int64_t cap) {
+  if (int rc = require_ready(c)) return rc;
+  if (int rc = check_instance(c, instance)) return rc;
+  if (cap < 0) return set_err(DEM_EINVAL, "cap must be >= 0");
+  if (c->cap >= ((int64_t)1 << 31))
+    return set_err(DEM_EINVAL, "%lld list entries: too many for 32-bit pair offsets",
+                   (long long)c->cap);
+  return wait_user(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_get_contacts_device(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
+                            double* delta_t, uint8_t* touching, int64_t* n_out) {
+  if (int rc = contacts_device_check(c, instance, cap)) return rc;
+  int* scratch = nullptr;
+  const size_t bytes = (size_t)pairs_scratch_ints(c->n) * sizeof(int);
+  HIPCHK(hipMalloc((void**)&scratch, bytes));
+  const int rc = contacts_device(c, instance, cap, pairs, delta_t, touching, n_out, scratch);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(scratch);
+  return rc;
+}
+
 int dem_record_contact_forces(dem_ctx* c, int32_t enable) {
   if (!c) return set_err(DEM_EINVAL, "null context");
   if (int rc = wait_user(c)) return rc;

@@ -231,4 +231,14 @@ hipError_t launch_tick(int64_t* clock, int64_t k, hipStream_t s);
 hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* info,
                         NbrList l, WallSlots ws, unsigned long long* out, hipStream_t s);
 
+// Candidate pairs of instance inst on the device (see dem_get_contacts_device).
+// scratch holds pairs_scratch_ints(sp.n) ints: block counts, their exclusive
+// scan (scratch[nb + nb] is the total afterwards) and the scan's tile sums.
+int64_t pairs_scratch_ints(int n);
+hipError_t launch_pairs_count(const StepParams& sp, int inst, const int* info, const int* gid,
+                              NbrList l, int* scratch, hipStream_t s);
+hipError_t launch_pairs_fill(const StepParams& sp, int inst, int gid_base, const double4* pos,
+                             const int* info, const int* gid, NbrList l, const int* scratch,
+                             int64_t* pairs, double* delta_t, uint8_t* touching, hipStream_t s);
+
 }  // namespace demgpu

@@ -1042,25 +1042,95 @@ __device__ __forceinline__ double drift_scale(const StepParams& sp,
   return sp.drift_scale > 0.0 ? sp.drift_scale : sp.dt * inst[inf >> kInstShift].ihs;
 }
 
-// Walls, the mesh contribution and the integration of particle i, whose
-// pair forces F and torques T are summed; returns the squared drift of this
-// step in units of half the instance's skin (for the dynamic search trigger)
-// when asked for it.
-template <typename R, int MODE, int MODEL>
-__device__ __forceinline__ double finish_particle(
+// Forces on particle i and its integration; returns the squared drift of
+// this step in units of half the instance's skin (for the dynamic search
+// trigger) when asked for it.
+template <typename R, int MODE, int MODEL, bool REC, typename TileT>
+__device__ __forceinline__ double force_particle(
     const int i, const StepParams& sp, const InstDev* __restrict__ inst,
-    const PairCoef* __restrict__ pwc, const WallDev* __restrict__ walls, ParticleBufs out,
-    const int inf, WallSlots ws, double4* __restrict__ Fo, double4* __restrict__ To,
-    const int64_t* __restrict__ clock, int64_t step_rel, const bool want_drift,
-    const int* __restrict__ xsel, const double4* __restrict__ Fx,
-    const double4* __restrict__ Tx, double4 xi, double4 vi, double4 wi, double F[3],
-    double T[3]) {
+    const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
+    const WallDev* __restrict__ walls, ParticleBufs in, ParticleBufs out,
+    const int* __restrict__ info, NbrList l, WallSlots ws, double4* __restrict__ Fo,
+    double4* __restrict__ To, const int64_t* __restrict__ clock, int64_t step_rel,
+    const int* __restrict__ flags, const bool want_drift, const int* __restrict__ xsel,
+    const double4* __restrict__ Fx, const double4* __restrict__ Tx, const TileT& tile,
+    const int len, const int jr0, double* __restrict__ pf) {
   const int n = sp.n;
-  const double dt = sp.dt;
+  double4 xi = tile.pos(in, i);
+  double4 vi = tile.vel(in, i);
+  double4 wi = tile.omg(in, i);
+  const int inf = tile.info(info, i);
+  // frozen after an error, and for inactive particles: carry the state over
+  if ((inf & kInactive) || *flags != 0) {
+    out.pos[i] = xi;
+    out.vel[i] = vi;
+    out.omg[i] = wi;
+    if (MODE != 0) {
+      Fo[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+      To[i] = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+    return 0.0;
+  }
   // material-pair row of (instance, type i): instance b's table starts at
   // b * kMaxTypes^2, so it follows from the info word without a lookup
-  const int row = ((inf >> kInstShift) * kMaxTypes + (inf & kTypeMask)) * kMaxTypes;
+  const int ti = inf & kTypeMask;
+  const int row = ((inf >> kInstShift) * kMaxTypes + ti) * kMaxTypes;
+  const PairCoef* __restrict__ ppi = ppc + row;
   const PairCoef* __restrict__ pwi = pwc + row;
+  const double dt = sp.dt;
+  double F[3] = {0.0, 0.0, 0.0};
+  double T[3] = {0.0, 0.0, 0.0};
+  const int max_nb = sp.max_nb;
+  const int64_t cap = l.cap;
+  // the index of entry k + 1 is loaded while entry k is worked on (the
+  // row walk is a chain of dependent loads; one index ahead costs one VGPR);
+  // the row length and entry 0 come from the caller
+  int jr_next = jr0;
+  for (int k = 0; k < len; ++k) {
+    const int64_t e = nbr_entry(i, k, max_nb);
+    const int jr = jr_next;
+    if (k + 1 < len) jr_next = ld_own(l.nbr + e + 64);  // entry (i, k + 1)
+    const int j = jr & kIndexMask;
+    // a pair touching at the last evaluation most likely still touches: its
+    // history is loaded together with the neighbour's position
+    double dtl[3] = {0.0, 0.0, 0.0};
+    if (jr & kTouchedBit) {
+      dtl[0] = ld_own(l.hist + e);
+      dtl[1] = ld_own(l.hist + cap + e);
+      dtl[2] = ld_own(l.hist + 2 * cap + e);
+    }
+    const double4 xj = tile.pos(in, j);
+    const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double rsum = xi.w + xj.w;
+    if (d2 < rsum * rsum) {
+      const double4 vj = tile.vel(in, j);
+      const double4 wj = tile.omg(in, j);
+      const int tj = tile.info(info, j) & kTypeMask;
+      double Fi[3], Mi[3];
+      pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      st_own(dtl[0], l.hist + e);
+      st_own(dtl[1], l.hist + cap + e);
+      st_own(dtl[2], l.hist + 2 * cap + e);
+      if (!(jr & kTouchedBit)) st_own(j | kTouchedBit, l.nbr + e);
+      if (REC) {
+        pf[e] = Fi[0];
+        pf[cap + e] = Fi[1];
+        pf[2 * cap + e] = Fi[2];
+      }
+      F[0] += Fi[0];
+      F[1] += Fi[1];
+      F[2] += Fi[2];
+      T[0] += Mi[0];
+      T[1] += Mi[1];
+      T[2] += Mi[2];
+    } else if (jr & kTouchedBit) {
+      st_own(0.0, l.hist + e);
+      st_own(0.0, l.hist + cap + e);
+      st_own(0.0, l.hist + 2 * cap + e);
+      st_own(j, l.nbr + e);
+    }
+  }
   // walls: time of this force evaluation
   const double t = (double)(*clock + step_rel) * dt;
   for (int s = 0; s < kWallSlots; ++s) {
@@ -1147,7 +1217,6 @@ __device__ __forceinline__ double finish_particle(
   return drift;
 }
 
-
 // Largest value of a wavefront (shuffles), then one atomic per wavefront on
 // one of kDriftSpread words: non-negative doubles order like their bit
 // patterns.  Every lane of the wavefront calls it; waves_per_block is the
@@ -1161,110 +1230,12 @@ __device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v,
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
 }
 
-// Per-wavefront work queue of the force kernel.  The row walk finds the
-// touching pairs of the wavefront's 64 particles entry by entry (all rows
-// advance together: entry k of every row, then entry k + 1); the touching
-// ones of each entry index are compacted into the queue with a ballot and a
-// lane-prefix count, so that the queue holds them in the order (k, lane).
-// When the next entry could overflow it, the queue is drained: every lane
-// evaluates the contact law of one queued pair, writes the pair's force and
-// torque on the row's particle to the queue, and then every particle adds
-// the contributions of its own pairs in the order of its row.  The sums are
-// therefore formed in exactly the order of a row walk, while the law runs on
-// all 64 lanes instead of on the lanes whose current entry touches.
-template <typename R>
-struct WaveQueue {
-  int jr[kWave];                 // neighbour word of the queued pair (index | touched bit)
-  int ok[kWave];                 // owner lane | row entry k << 8
-  R f[6][kWave];                 // force (x, y, z) and torque (x, y, z) on the owner
-  unsigned long long lm[kWave];  // ballot of each non-empty entry index in the queue
-  int lp[kWave];                 // queue position of that entry index's first pair
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// number of set bits of m below this lane
-__device__ __forceinline__ int lanes_below(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
-// Drain a wavefront's queue of qn pairs (nl non-empty entry indices): the law
-// for pair p on lane p, then each owner's sum over its queued pairs in row
-// order.  wb is the sorted index of the wavefront's first particle and tb its
-// first slot in the tile.
-template <typename R, int MODEL, typename TileT>
-__device__ __forceinline__ void drain_queue(
-    WaveQueue<R>& q, const int qn, const int nl, const int lane, const int wb, const int tb,
-    const StepParams& sp, const PairCoef* __restrict__ ppc, ParticleBufs in,
-    const int* __restrict__ info, const NbrList& l, double* __restrict__ pf,
-    const TileT& tile, double F[3], double T[3]) {
-  wave_sync();
-  if (lane < qn) {
-    const int jr = q.jr[lane];
-    const int okv = q.ok[lane];
-    const int o = okv & (kWave - 1);
-    const int k = okv >> 8;
-    const int io = wb + o;
-    const int64_t e = nbr_entry(io, k, sp.max_nb);
-    const int64_t cap = l.cap;
-    double dtl[3] = {0.0, 0.0, 0.0};
-    if (jr & kTouchedBit) {
-      dtl[0] = ld_own(l.hist + e);
-      dtl[1] = ld_own(l.hist + cap + e);
-      dtl[2] = ld_own(l.hist + 2 * cap + e);
-    }
-    const int j = jr & kIndexMask;
-    const double4 xo = tile.p[tb + o], vo = tile.v[tb + o], wo = tile.w[tb + o];
-    const int inf = tile.in[tb + o];
-    const double4 xj = tile.pos(in, j);
-    const double4 vj = tile.vel(in, j);
-    const double4 wj = tile.omg(in, j);
-    const int tj = tile.info(info, j) & kTypeMask;
-    const int row = ((inf >> kInstShift) * kMaxTypes + (inf & kTypeMask)) * kMaxTypes;
-    double Fi[3], Mi[3];
-    pp_contact<R>(ppc[row + tj], sp.rolling, MODEL, sp.dt, xo, vo, wo, xj, vj, wj, dtl, Fi, Mi);
-    st_own(dtl[0], l.hist + e);
-    st_own(dtl[1], l.hist + cap + e);
-    st_own(dtl[2], l.hist + 2 * cap + e);
-    if (!(jr & kTouchedBit)) st_own(j | kTouchedBit, l.nbr + e);
-    if (pf) {
-      pf[e] = Fi[0];
-      pf[cap + e] = Fi[1];
-      pf[2 * cap + e] = Fi[2];
-    }
-    // exact: the FP32 law's results are floats widened to double
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      q.f[c][lane] = (R)Fi[c];
-      q.f[3 + c][lane] = (R)Mi[c];
-    }
-  }
-  wave_sync();
-  for (int r = 0; r < nl; ++r) {
-    const unsigned long long m = q.lm[r];
-    if ((m >> lane) & 1ull) {
-      const int p = q.lp[r] + lanes_below(m);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        F[c] += (double)q.f[c][p];
-        T[c] += (double)q.f[3 + c][p];
-      }
-    }
-  }
-  wave_sync();
-}
-
 // Occupancy floor: four wavefronts per SIMD (128 VGPRs, no spills), except
-// for the linear law with explicit Euler, which keeps three.
-//
-// One thread per particle (its row, walls, mesh contribution and
-// integration); the pairs of the rows go through the wavefront's queue.
-template <typename R, int MODE, int MODEL, int BS>
+// for the linear law with explicit Euler, which would spill there and keeps
+// three.
+// REC: also write every touching pair's force to pf (the per-contact record;
+// a separate instantiation, so the record costs the plain kernel nothing).
+template <typename R, int MODE, int MODEL, int BS, bool REC>
 __global__ void __launch_bounds__(BS)
     __attribute__((amdgpu_waves_per_eu(MODE == 2 && MODEL == 1 ? 3 : 4)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
@@ -1276,99 +1247,21 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
         const double4* __restrict__ Tx, double* __restrict__ pf) {
   const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int tb = threadIdx.x & ~(kWave - 1);  // the wavefront's first tile slot
-  const int n = sp.n;
-  const int max_nb = sp.max_nb;
   // the row length and the first row entry do not depend on the tile: their
   // loads are issued before it is staged (entry 0 exists for every row)
-  int len = 0, jr_next = 0;
-  if (i < n) {
+  int len = 0, jr0 = 0;
+  if (i < sp.n) {
     len = ld_own(l.rowlen + i);
-    jr_next = ld_own(l.nbr + nbr_entry(i, 0, max_nb));
+    jr0 = ld_own(l.nbr + nbr_entry(i, 0, sp.max_nb));
   }
   __shared__ Tile<BS> tile;
-  __shared__ WaveQueue<R> wq[BS / kWave];
-  WaveQueue<R>& q = wq[threadIdx.x / kWave];
-  tile.stage(in, info, b0, n);
+  tile.stage(in, info, b0, sp.n);
   __syncthreads();
-  const bool valid = i < n;
-  const int inf = valid ? tile.in[threadIdx.x] : kInactive;
-  // frozen after an error, and for inactive particles: the state is carried over
-  const bool live = valid && !(inf & kInactive) && *flags == 0;
-  if (!live) len = 0;
-  double4 xi = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (valid) xi = tile.p[threadIdx.x];
-  double F[3] = {0.0, 0.0, 0.0};
-  double T[3] = {0.0, 0.0, 0.0};
-  // longest row of the wavefront (uniform across its lanes)
-  int wl = len;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) wl = max(wl, __shfl_xor(wl, o, kWave));
-  wl = __builtin_amdgcn_readfirstlane(wl);
-  int qn = 0, nl = 0;  // queued pairs, non-empty entry indices in the queue
-  for (int k = 0; k < wl; ++k) {
-    bool touch = false;
-    int jr = 0;
-    if (k < len) {
-      const int64_t e = nbr_entry(i, k, max_nb);
-      jr = jr_next;
-      // the index of entry k + 1 is loaded while entry k is worked on
-      if (k + 1 < len) jr_next = ld_own(l.nbr + e + kWave);
-      const int j = jr & kIndexMask;
-      const double4 xj = tile.pos(in, j);
-      const double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-      const double d2 = (dx * dx + dy * dy) + dz * dz;
-      const double rsum = xi.w + xj.w;
-      touch = d2 < rsum * rsum;
-      if (!touch && (jr & kTouchedBit)) {
-        // the pair stopped touching: its history restarts at zero
-        st_own(0.0, l.hist + e);
-        st_own(0.0, l.hist + l.cap + e);
-        st_own(0.0, l.hist + 2 * l.cap + e);
-        st_own(j, l.nbr + e);
-      }
-    }
-    const unsigned long long m = __ballot(touch);
-    if (m == 0ull) continue;
-    const int c = __popcll(m);
-    if (qn + c > kWave) {
-      drain_queue<R, MODEL>(q, qn, nl, lane, b0 + tb, tb, sp, ppc, in, info, l, pf, tile, F, T);
-      qn = 0;
-      nl = 0;
-    }
-    if (touch) {
-      const int p = qn + lanes_below(m);
-      q.jr[p] = jr;
-      q.ok[p] = lane | (k << 8);
-    }
-    if (lane == 0) {
-      q.lm[nl] = m;
-      q.lp[nl] = qn;
-    }
-    qn += c;
-    nl += 1;
-  }
-  if (qn > 0)
-    drain_queue<R, MODEL>(q, qn, nl, lane, b0 + tb, tb, sp, ppc, in, info, l, pf, tile, F, T);
   double d = 0.0;
-  if (valid) {
-    double4 vi = tile.v[threadIdx.x];
-    double4 wi = tile.w[threadIdx.x];
-    if (!live) {
-      out.pos[i] = xi;
-      out.vel[i] = vi;
-      out.omg[i] = wi;
-      if (MODE != 0) {
-        Fo[i] = make_double4(0.0, 0.0, 0.0, 0.0);
-        To[i] = make_double4(0.0, 0.0, 0.0, 0.0);
-      }
-    } else {
-      d = finish_particle<R, MODE, MODEL>(i, sp, inst, pwc, walls, out, inf, ws, Fo, To, clock,
-                                          step_rel, drift != nullptr, xsel, Fx, Tx, xi, vi, wi,
-                                          F, T);
-    }
-  }
+  if (i < sp.n)
+    d = force_particle<R, MODE, MODEL, REC>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
+                                       To, clock, step_rel, flags, drift != nullptr, xsel, Fx,
+                                       Tx, tile, len, jr0, pf);
   if (drift) wave_max_to(drift, d, BS / 64);
 }
 
@@ -1383,17 +1276,25 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
   if (sp.n <= 0) return hipSuccess;
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   dim3 gr(grid_for(sp.n, block)), bl(block);
-#define DEM_LAUNCH(RT, M, L)                                                                  \
-  do {                                                                                        \
-    if (block == 64)                                                                          \
-      hipLaunchKernelGGL((k_force<RT, M, L, 64>), gr, bl, 0, s, sp, inst, pp, pw, walls, in,  \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx, pf);              \
-    else if (block == 128)                                                                    \
-      hipLaunchKernelGGL((k_force<RT, M, L, 128>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx, pf);              \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_force<RT, M, L, 256>), gr, bl, 0, s, sp, inst, pp, pw, walls, in, \
-                         out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx, Tx, pf);              \
+#define DEM_LAUNCH_REC(RT, M, L, REC)                                                          \
+  do {                                                                                          \
+    if (block == 64)                                                                            \
+      hipLaunchKernelGGL((k_force<RT, M, L, 64, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,   \
+                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
+                         Tx, pf);                                                               \
+    else if (block == 128)                                                                      \
+      hipLaunchKernelGGL((k_force<RT, M, L, 128, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,  \
+                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
+                         Tx, pf);                                                               \
+    else                                                                                        \
+      hipLaunchKernelGGL((k_force<RT, M, L, 256, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,  \
+                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
+                         Tx, pf);                                                               \
+  } while (0)
+#define DEM_LAUNCH(RT, M, L)                         \
+  do {                                               \
+    if (pf) DEM_LAUNCH_REC(RT, M, L, true);          \
+    else DEM_LAUNCH_REC(RT, M, L, false);            \
   } while (0)
 #define DEM_LAUNCH_MODE(RT, L)                \
   do {                                        \
@@ -1410,6 +1311,7 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
   }
 #undef DEM_LAUNCH_MODE
 #undef DEM_LAUNCH
+#undef DEM_LAUNCH_REC
   return hipGetLastError();
 }
 
@@ -1669,6 +1571,114 @@ hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* inf
   if (sp.n <= 0) return hipSuccess;
   unsigned nb = (unsigned)((sp.n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_stats, dim3(nb), dim3(kBlock), 0, s, sp, pos, info, l, ws, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ contact list on the device
+//
+// The candidate pairs of one instance, each once as (gid_i, gid_j) with
+// gid_i < gid_j, written to caller buffers in the sorted order of the first
+// particle and then its row order: a per-block count, a scan of the block
+// counts, and a fill in which each block recounts its threads' pairs and
+// places them after its block's offset.  Only the block counts and their
+// scan need memory beyond the outputs.
+
+__device__ __forceinline__ int pairs_of_row(const StepParams& sp, int inst, int p,
+                                            const int* __restrict__ info,
+                                            const int* __restrict__ gid, const NbrList& l) {
+  if (p >= sp.n) return 0;
+  const int inf = info[p];
+  if ((inf & kInactive) || (inf >> kInstShift) != inst) return 0;
+  const int g = gid[p];
+  const int len = l.rowlen[p];
+  int c = 0;
+  for (int k = 0; k < len; ++k) {
+    const int q = l.nbr[nbr_entry(p, k, sp.max_nb)] & kIndexMask;
+    c += gid[q] > g ? 1 : 0;
+  }
+  return c;
+}
+
+__global__ void k_pairs_count(StepParams sp, int inst, const int* __restrict__ info,
+                              const int* __restrict__ gid, NbrList l, int* __restrict__ bcount) {
+  __shared__ int sh[4];
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int c = pairs_of_row(sp, inst, p, info, gid, l);
+  int tot;
+  block_exclusive_scan(c, sh, &tot);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+__global__ void k_pairs_fill(StepParams sp, int inst, int gid_base,
+                             const double4* __restrict__ pos, const int* __restrict__ info,
+                             const int* __restrict__ gid, NbrList l,
+                             const int* __restrict__ bstart, int64_t* __restrict__ pairs,
+                             double* __restrict__ delta_t, uint8_t* __restrict__ touching) {
+  __shared__ int sh[4];
+  const int p = blockIdx.x * kBlock + threadIdx.x;
+  const int c = pairs_of_row(sp, inst, p, info, gid, l);
+  int tot;
+  int64_t o = (int64_t)bstart[blockIdx.x] + block_exclusive_scan(c, sh, &tot);
+  if (c == 0) return;
+  const int g = gid[p];
+  const double4 xp = pos[p];
+  const int len = l.rowlen[p];
+  for (int k = 0; k < len; ++k) {
+    const int64_t e = nbr_entry(p, k, sp.max_nb);
+    const int jr = l.nbr[e];
+    const int q = jr & kIndexMask;
+    const int gq = gid[q];
+    if (!(gq > g)) continue;
+    if (pairs) {
+      pairs[2 * o] = g - gid_base;
+      pairs[2 * o + 1] = gq - gid_base;
+    }
+    if (delta_t) {
+      // bit 31: the pair touched at the last evaluation and holds a history
+      const bool h = (jr & kTouchedBit) != 0;
+      delta_t[3 * o] = h ? l.hist[e] : 0.0;
+      delta_t[3 * o + 1] = h ? l.hist[l.cap + e] : 0.0;
+      delta_t[3 * o + 2] = h ? l.hist[2 * l.cap + e] : 0.0;
+    }
+    if (touching) {
+      const double4 xq = pos[q];
+      const double dx = xq.x - xp.x, dy = xq.y - xp.y, dz = xq.z - xp.z;
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      const double rs = xp.w + xq.w;
+      touching[o] = d2 < rs * rs ? 1 : 0;
+    }
+    ++o;
+  }
+}
+
+int64_t pairs_scratch_ints(int n) {
+  const int64_t nb = (n + kBlock - 1) / kBlock;
+  return nb + (nb + 2) + ((nb + 1 + kScanTile - 1) / kScanTile + 1);
+}
+
+hipError_t launch_pairs_count(const StepParams& sp, int inst, const int* info, const int* gid,
+                              NbrList l, int* scratch, hipStream_t s) {
+  const int64_t nb = (sp.n + kBlock - 1) / kBlock;
+  int* bcount = scratch;
+  int* bstart = scratch + nb;
+  int* tiles = bstart + nb + 2;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_pairs_count, dim3((unsigned)nb), dim3(kBlock), 0, s, sp, inst, info,
+                       gid, l, bcount);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nb == 0) return launch_fill_i32(bstart, 0, 1, s);
+  return launch_scan(bcount, bstart, nb, tiles, s);
+}
+
+hipError_t launch_pairs_fill(const StepParams& sp, int inst, int gid_base, const double4* pos,
+                             const int* info, const int* gid, NbrList l, const int* scratch,
+                             int64_t* pairs, double* delta_t, uint8_t* touching,
+                             hipStream_t s) {
+  const int64_t nb = (sp.n + kBlock - 1) / kBlock;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pairs_fill, dim3((unsigned)nb), dim3(kBlock), 0, s, sp, inst, gid_base,
+                     pos, info, gid, l, scratch + nb, pairs, delta_t, touching);
   return hipGetLastError();
 }
 

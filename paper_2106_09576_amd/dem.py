@@ -103,6 +103,7 @@ SIGNATURES = {
     "dem_get_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, U8P, I64P]),
     "dem_get_wall_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_record_contact_forces": (C.c_int, [P, C.c_int32]),
+    "dem_get_contacts_device": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, I64P]),
     "dem_get_contact_forces": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_add_mesh_wall": (C.c_int, [P, C.c_int32, C.c_int64, DP, C.c_int64, I32P, C.c_int32, DP,
                                     DP, C.c_double, C.c_double, I32P]),
@@ -309,6 +310,27 @@ class Dem:
         self._check(self._lib.dem_get_contacts(self._h, instance, max(m, 1), pairs.ctypes.data_as(I64P),
                                                _d(dt), touch.ctypes.data_as(U8P), C.byref(cnt)))
         return pairs[:m], dt[:m], touch[:m].astype(bool)
+
+    def get_contacts_device(self, cap, pairs_ptr=None, delta_t_ptr=None, touching_ptr=None,
+                            instance=0):
+        """Candidate pairs into device buffers given by address (e.g. a
+        tensor's data_ptr(); int64 [cap, 2], float64 [cap, 3], uint8 [cap]),
+        in the library's spatial order; returns the count.  Raises DemError
+        (DEM_EINVAL) when the count exceeds cap."""
+        cnt = C.c_int64()
+        self._check(self._lib.dem_get_contacts_device(self._h, instance, int(cap), pairs_ptr,
+                                                      delta_t_ptr, touching_ptr,
+                                                      C.byref(cnt)))
+        return cnt.value
+
+    def count_contacts_device(self, instance=0):
+        """Number of candidate pairs (a dem_get_contacts_device call with cap 0)."""
+        cnt = C.c_int64()
+        rc = self._lib.dem_get_contacts_device(self._h, instance, 0, None, None, None,
+                                               C.byref(cnt))
+        if rc not in (DEM_OK, DEM_EINVAL):
+            self._check(rc)
+        return cnt.value
 
     def record_contact_forces(self, enable=True):
         self._check(self._lib.dem_record_contact_forces(self._h, 1 if enable else 0))
