@@ -336,6 +336,20 @@ int dem_get_contacts(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs
    has 2^31 entries or more. */
 int dem_get_contacts_device(dem_ctx* ctx, int32_t instance, int64_t cap, int64_t* pairs,
                             double* delta_t, uint8_t* touching, int64_t* n_out);
+/* dem_get_contacts_device for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the same pairs in the same order, but the workspace is a
+   file-scope device array of the library (512 KiB per GPU, held until the
+   process ends; its address is looked up once per device, on the first call
+   with that device current) instead of a per-call allocation.  Contexts of
+   at most 2^24 particles (DEM_EINVAL beyond, and when the context's device
+   is not the current one).  Every call on a GPU shares that GPU's workspace:
+   calls that overlap on one GPU (several host threads, or contexts on other
+   streams) race and must be serialised by the caller.  Allocates nothing,
+   host or device. */
+int dem_get_contacts_device_noalloc(dem_ctx* ctx, int32_t instance, int64_t cap,
+                                    int64_t* pairs, double* delta_t, uint8_t* touching,
+                                    int64_t* n_out);
 /* Per-contact force record, for error measures per contact.  While enabled
    (enable != 0; off by default), every force evaluation also writes the force
    F^n + F^t (Eqs. normal_force and tangential_force after the Coulomb limit of

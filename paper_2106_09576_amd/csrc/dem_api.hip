@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2114,6 +2115,71 @@ int dem_get_contacts_device(dem_ctx* c, int32_t instance, int64_t cap, int64_t* 
   (void)hipStreamSynchronize(c->stream);
   (void)hipFree(scratch);
   return rc;
+}
+
+// ------------------------------------------------------ allocation-free variant
+//
+// dem_get_contacts_device_noalloc keeps its workspace in `scratch`, a
+// file-scope device array: one copy per GPU, held until the process ends,
+// shared by every call on that GPU (calls that overlap on one GPU race).
+// On the host the array's name stands for a host-side shadow, not a device
+// address, so host code never hands it to a kernel or a copy: it uses the
+// device address hipGetSymbolAddress returns, looked up once per device with
+// that device current.  Every word the call reads is written by the same
+// call first, so nothing needs clearing between calls.
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kNoAllocMaxParticles = 1 << 24;
+constexpr int64_t kNoAllocBlocks = kNoAllocMaxParticles / kBlock;
+// block counts, their scan (one more word), the scan's tile sums
+constexpr int64_t kNoAllocScratchInts =
+    kNoAllocBlocks + (kNoAllocBlocks + 2) + ((kNoAllocBlocks + 1 + 1023) / 1024 + 1);
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) int scratch[kNoAllocScratchInts];
+
+std::mutex g_scratch_mu;
+int* g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// device address of `scratch` on device dev (current)
+int noalloc_scratch(int dev, int** out) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return set_err(DEM_ENODEV, "device %d beyond the %d the workspace table holds", dev,
+                   kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_err(DEM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                     hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<int*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return DEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dem_get_contacts_device_noalloc(dem_ctx* c, int32_t instance, int64_t cap, int64_t* pairs,
+                                    double* delta_t, uint8_t* touching, int64_t* n_out) {
+  if (int rc = contacts_device_check(c, instance, cap)) return rc;
+  if (pairs_scratch_ints(c->n) > kNoAllocScratchInts)
+    return set_err(DEM_EINVAL, "%d particles: the allocation-free workspace holds %d", c->n,
+                   kNoAllocMaxParticles);
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != c->device)
+    return set_err(DEM_EINVAL, "the context lives on device %d but device %d is current",
+                   c->device, dev);
+  int* ws = nullptr;
+  if (int rc = noalloc_scratch(dev, &ws)) return rc;
+  return contacts_device(c, instance, cap, pairs, delta_t, touching, n_out, ws);
 }
 
 int dem_record_contact_forces(dem_ctx* c, int32_t enable) {

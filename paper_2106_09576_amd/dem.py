@@ -104,6 +104,7 @@ SIGNATURES = {
     "dem_get_wall_contacts": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_record_contact_forces": (C.c_int, [P, C.c_int32]),
     "dem_get_contacts_device": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, I64P]),
+    "dem_get_contacts_device_noalloc": (C.c_int, [P, C.c_int32, C.c_int64, P, P, P, I64P]),
     "dem_get_contact_forces": (C.c_int, [P, C.c_int32, C.c_int64, I64P, DP, I64P]),
     "dem_add_mesh_wall": (C.c_int, [P, C.c_int32, C.c_int64, DP, C.c_int64, I32P, C.c_int32, DP,
                                     DP, C.c_double, C.c_double, I32P]),
@@ -321,6 +322,15 @@ class Dem:
         self._check(self._lib.dem_get_contacts_device(self._h, instance, int(cap), pairs_ptr,
                                                       delta_t_ptr, touching_ptr,
                                                       C.byref(cnt)))
+        return cnt.value
+
+    def get_contacts_device_noalloc(self, cap, pairs_ptr=None, delta_t_ptr=None,
+                                    touching_ptr=None, instance=0):
+        """As get_contacts_device, through the entry point that allocates
+        nothing (its workspace is a device array of the library)."""
+        cnt = C.c_int64()
+        self._check(self._lib.dem_get_contacts_device_noalloc(
+            self._h, instance, int(cap), pairs_ptr, delta_t_ptr, touching_ptr, C.byref(cnt)))
         return cnt.value
 
     def count_contacts_device(self, instance=0):
