@@ -288,33 +288,53 @@ def measure_silos(args, precs):
     [2, 3] mm, 30 degree wedge to a 12 mm slot, dt = 5e-6 s) and the
     cylindrical silo of 4.3M spheres (log-normal d, 60 degree cone to a 40 mm
     outlet, E = 1e7 Pa, dt = 2e-6 s).  The spheres start at rest on a lattice
-    above the plugged outlet and fall into a bed (untimed fill); the plug
-    switches off at the end of the fill, and after the warmup steps the
+    above the plugged outlet (spacing of the largest diameter, so the column
+    is about three times as tall as the bed it forms).  Fill (untimed): the
+    spheres fall into a bed, in a context of its own with a time step five
+    times the run's (below 12 % of the smallest sphere's Rayleigh time).  The
+    filled positions, velocities and spins then start the run at the
+    workload's time step with the plug gone; after the warmup steps the
     discharge is timed (spheres leaving the domain below the outlet become
     inactive; the rate counts active particle-steps).  Dynamic search,
     64-thread force workgroups."""
+    import numpy as np
     import workloads as W
+    from paper_2106_09576_amd import Dem
     out = {}
-    legs = (("wedge_silo", args.silo_fill, args.silo_steps,
-             lambda t_open: W.wedge_silo_scene(t_open=t_open), 5.0e-6),
-            ("hopper_silo", args.hopper_fill, args.hopper_steps,
-             lambda t_open: W.hopper_silo_scene(t_open=t_open), 2.0e-6))
+    legs = (("wedge_silo", args.silo_fill, args.silo_steps, W.wedge_silo_scene, 5.0e-6),
+            ("hopper_silo", args.hopper_fill, args.hopper_steps, W.hopper_silo_scene, 2.0e-6))
     for name, fill, steps, make, dt in legs:
         log(f"{name}: building the scene")
-        sc = make(fill * dt)
+        sc = make(t_open=1.0)  # the plug (the one wall with an end time) outlasts the fill
         sc = dict(sc, config=dict(sc["config"], rebuild_interval=0))
+        fill_sc = dict(sc, config=dict(sc["config"], dt=5 * dt))
+        log(f"{name}: filling, {fill} steps of {5 * dt:g} s")
+        f = Dem.from_scene(fill_sc, precision="fp32", force_block=MAIN_FORCE_BLOCK)
+        run_steps(f, fill, f"{name}: fill")
+        st = f.get_state()
+        fs = f.get_stats()
+        f.close()
+        a = st["active"].astype(bool)
+        # the run: filled state, plug (the floating wall) gone
+        walls = [w for w in sc["walls"] if not np.isfinite(w["t_off"])]
+        run_sc = dict(sc, walls=walls,
+                      particles={k: np.ascontiguousarray(v[a]) for k, v in
+                                 dict(sc["particles"], pos=st["pos"], vel=st["vel"],
+                                      omega=st["omega"]).items()})
         res = {}
         for p in precs:
-            r = measure(args, p, sc, label=f"{p} {name}", force_block=MAIN_FORCE_BLOCK,
-                        settle=fill, steps=steps)
+            r = measure(args, p, run_sc, label=f"{p} {name}", force_block=MAIN_FORCE_BLOCK,
+                        settle=0, steps=steps)
             r["force_kernel_frac_of_peak"] = r["force_kernel_gbs"] / HBM_PEAK_GBS
             res[p] = r
         g = sc["geometry"]
         out[name] = {"workload": (f"{name.replace('_', ' ')}, {sc['particles']['pos'].shape[0]} "
                                   f"spheres, geometry {g}, dt={dt:g} s, r_s=1.3 d_max, "
-                                  f"dynamic search; fill of {fill} steps with the outlet "
-                                  f"plugged, the plug off at its end, {args.warmup} warmup "
-                                  f"steps, then {steps} discharge steps timed"),
+                                  f"dynamic search; filled for {fill} steps of {5 * dt:g} s "
+                                  f"with the outlet plugged ({fs['n_touching'] / 2 / max(fs['n_active'], 1):.2f} "
+                                  f"touching pairs per sphere at its end), then the plug "
+                                  f"removed, {args.warmup} warmup steps and {steps} discharge "
+                                  f"steps timed"),
                      "results": res}
         if "fp32" in res and "fp64" in res:
             out[name]["fp32_vs_fp64"] = res["fp32"]["value"] / res["fp64"]["value"]
@@ -508,11 +528,12 @@ def main():
     ap.add_argument("--skip-mesh", action="store_true", help="skip the meshed-drum leg")
     ap.add_argument("--skip-silos", action="store_true", help="skip the two silo legs")
     ap.add_argument("--silo-fill", type=int, default=20000,
-                    help="fill steps of the wedge silo before its outlet opens")
+                    help="fill steps (of five times the run's time step) of the wedge silo")
     ap.add_argument("--silo-steps", type=int, default=4000,
                     help="timed discharge steps of the wedge silo")
-    ap.add_argument("--hopper-fill", type=int, default=10000,
-                    help="fill steps of the 4.3M-sphere silo before its outlet opens")
+    ap.add_argument("--hopper-fill", type=int, default=30000,
+                    help="fill steps (of five times the run's time step) of the 4.3M-sphere "
+                         "silo")
     ap.add_argument("--hopper-steps", type=int, default=1000,
                     help="timed discharge steps of the 4.3M-sphere silo")
     ap.add_argument("--dam-n", type=int, default=1_280_000)
