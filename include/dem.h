@@ -226,7 +226,8 @@ int dem_set_wall_motion(dem_ctx* ctx, int32_t instance, int32_t wall_id,
    once every instance has particles.  Setting particles again restarts the
    whole batch from the inputs last given for each instance.  DEM_ECAPACITY
    (from the call that builds the batch) if a particle already has more
-   neighbours than max_neighbors. */
+   neighbours than max_neighbors; DEM_EINVAL if n or the batch's total
+   exceeds 2^29 particles. */
 int dem_set_particles(dem_ctx* ctx, int32_t instance, int64_t n, const double* pos,
                       const double* vel, const double* omega, const double* radius,
                       const int32_t* type);

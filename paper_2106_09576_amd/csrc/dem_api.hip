@@ -119,6 +119,10 @@ struct dem_ctx {
   int* nbr[2]{};
   double* hist[2]{};
   int* rowlen[2]{};
+  int* rowcut[2]{};  // per particle: the row cuts of each list
+  // displacement bound of the row cuts (StepParams::bacc, brec)
+  double* d_bacc = nullptr;
+  unsigned long long* d_brec = nullptr;
   uint32_t* keys = nullptr;
   int *rank = nullptr, *count = nullptr, *start = nullptr, *tile_sums = nullptr;
   int *perm0 = nullptr, *perm = nullptr, *inv = nullptr;
@@ -303,15 +307,30 @@ PairCoef make_coef(const dem_config& cfg, double Ye, double Ge, double e, double
 // ------------------------------------------------------------ kernel groups
 
 ParticleBufs pbufs(dem_ctx* c, int k) { return ParticleBufs{c->pos[k], c->vel[k], c->omg[k]}; }
-NbrList nlist(dem_ctx* c, int k) { return NbrList{c->nbr[k], c->hist[k], c->rowlen[k], c->cap}; }
+NbrList nlist(dem_ctx* c, int k) {
+  return NbrList{c->nbr[k], c->hist[k], c->rowlen[k], c->cap, c->rowcut[k]};
+}
+
+// Step offset (from the device clock) of the next force evaluation after
+// the current state: velocity Verlet first kicks and drifts to step + 1,
+// explicit Euler evaluates the current positions.  A search between dem_step
+// calls restarts the row cuts' displacement bound there.
+int64_t next_eval_rel(const dem_ctx* c) {
+  return (c->cfg.integrator == 0 ? c->step + 1 : c->step) - c->host_base;
+}
 WallSlots wslots(dem_ctx* c, int k) { return WallSlots{c->wid[k], c->whist[k]}; }
 MeshSlots mslots(dem_ctx* c, int k) { return MeshSlots{c->mtri[k], c->mhist[k]}; }
 MeshTables mtables(dem_ctx* c) { return MeshTables{c->d_tri, c->d_mcell, c->d_mcell_tri}; }
 
 // Contact search: counting sort into cells, reorder, particle-wall search and
 // particle-pair search with history carry-over.  Flips both parities.  The
-// search takes place at time (clock + step_rel) dt, where moving walls are.
-int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_rel) {
+// search takes place at time (clock + step_rel) dt, where moving walls are,
+// and restarts the displacement bound of the row cuts for the force
+// evaluation at step clock + bound_step_rel (the next one at these
+// positions; < 0: the same as step_rel, as for a search inside a step).
+int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_rel,
+                    int64_t bound_step_rel = -1) {
+  if (bound_step_rel < 0) bound_step_rel = step_rel;
   hipStream_t s = c->stream;
   const int a = c->cur, p = c->pcur;
   HIPCHK(launch_fill_i32(c->count, 0, c->n_keys + 1, s));
@@ -328,8 +347,8 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
                         c->d_walls, mtables(c), mslots(c, p), mslots(c, p ^ 1),
                         move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
-                        c->d_clock, step_rel, c->d_flags, s));
-  HIPCHK(launch_search(c->d_inst, c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
+                        c->d_clock, step_rel, bound_step_rel, c->d_flags, s));
+  HIPCHK(launch_search(c->d_inst, (int)c->inst.size(), c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
                        c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
   c->pcur ^= 1;
@@ -608,7 +627,8 @@ int step_dynamic(dem_ctx* c, int64_t n_steps) {
   if (vv) {
     HIPCHK(launch_fill_i32((int*)c->d_drift, 0, 2 * kDriftSpread, c->stream));
     HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
-                             c->F[c->pcur], c->T[c->pcur], c->d_drift, c->stream));
+                             c->F[c->pcur], c->T[c->pcur], c->d_drift, c->d_clock,
+                             s0 + 1 - c->host_base, c->stream));
     if ((rc = fold_drift(c, 0, 1))) return rc;
   }
   int64_t s = s0 + 1;
@@ -1004,7 +1024,7 @@ int commit(dem_ctx* c) {
   const int B = (int)c->inst.size();
   int64_t N = 0;
   for (const Instance& I : c->inst) N += I.n;
-  if (N > ((int64_t)1 << 30)) return set_err(DEM_EINVAL, "too many particles in the batch");
+  if (N > kMaxParticles) return set_err(DEM_EINVAL, "too many particles in the batch (at most 2^29)");
   const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
   int64_t total_keys = 0;
   double bound_nb = 16.0;
@@ -1106,6 +1126,7 @@ int commit(dem_ctx* c) {
     rc = rc ? rc : dalloc_t(c, &c->nbr[b], (size_t)std::max<int64_t>(c->cap, 1));
     rc = rc ? rc : dalloc_t(c, &c->hist[b], (size_t)std::max<int64_t>(c->cap, 1) * 3);
     rc = rc ? rc : dalloc_t(c, &c->rowlen[b], NN);
+    rc = rc ? rc : dalloc_t(c, &c->rowcut[b], NN);
   }
   rc = rc ? rc : dalloc_t(c, &c->xref, NN);
   rc = rc ? rc : dalloc_t(c, &c->keys, NN);
@@ -1125,6 +1146,8 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
   rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_bacc, 3);
+  rc = rc ? rc : dalloc_t(c, &c->d_brec, 3 * (size_t)kDriftSpread);
   if (c->record_pf)
     rc = rc ? rc : dalloc_t(c, &c->pair_force, (size_t)std::max<int64_t>(c->cap, 1) * 3);
   if (!htri.empty()) {
@@ -1242,6 +1265,10 @@ int commit(dem_ctx* c) {
     HIPCHK(hipMemcpyAsync(c->info[0], hinfo.data(), N * sizeof(int), hipMemcpyHostToDevice, s));
   }
   // zero-filled: forces of both parities, empty old list and wall slots
+  c->sp.bacc = c->d_bacc;
+  c->sp.brec = c->d_brec;
+  HIPCHK(launch_fill_i32((int*)c->d_bacc, 0, 6, s));
+  HIPCHK(launch_fill_i32((int*)c->d_brec, 0, 6 * kDriftSpread, s));
   HIPCHK(launch_fill_i32((int*)c->F[0], 0, (int64_t)NN * 8, s));
   HIPCHK(launch_fill_i32((int*)c->T[0], 0, (int64_t)NN * 8, s));
   HIPCHK(launch_fill_i32((int*)c->F[1], 0, (int64_t)NN * 8, s));
@@ -1254,7 +1281,7 @@ int commit(dem_ctx* c) {
   c->step = 0;
   c->host_base = 0;
   c->n_rebuilds = 0;
-  if ((rc = enqueue_rebuild(c, 0, 0, 0))) return rc;
+  if ((rc = enqueue_rebuild(c, 0, 0, 0, next_eval_rel(c)))) return rc;
   int flags = 0;
   if ((rc = read_flags(c, &flags))) return rc;
   c->ready = true;
@@ -1591,7 +1618,7 @@ int dem_set_particles(dem_ctx* c, int32_t instance, int64_t n, const double* pos
                       const int32_t* type) {
   if (!c) return set_err(DEM_EINVAL, "null context");
   if (int rc = check_instance(c, instance)) return rc;
-  if (n < 0 || n > (int64_t)1 << 30) return set_err(DEM_EINVAL, "n out of range");
+  if (n < 0 || n > kMaxParticles) return set_err(DEM_EINVAL, "n out of range (at most 2^29)");
   if (n > 0 && (!pos || !radius)) return set_err(DEM_EINVAL, "pos and radius are required");
   Instance& I = c->inst[(size_t)instance];
   for (int64_t i = 0; i < n; ++i) {
@@ -1647,7 +1674,7 @@ int dem_set_particles_device(dem_ctx* c, int32_t instance, int64_t n, const doub
                              const double* vel, const double* omega, const double* radius,
                              const int32_t* type) {
   if (!c) return set_err(DEM_EINVAL, "null context");
-  if (n < 0 || n > (int64_t)1 << 30) return set_err(DEM_EINVAL, "n out of range");
+  if (n < 0 || n > kMaxParticles) return set_err(DEM_EINVAL, "n out of range (at most 2^29)");
   // validation needs the values on the host; stage them once
   std::vector<double> hp(3 * (size_t)n), hv, hw, hr((size_t)n);
   std::vector<int32_t> ht;
@@ -1700,7 +1727,8 @@ int dem_step(dem_ctx* c, int64_t n_steps) {
   if (graphs && n_steps >= K && (rc = prepare_chunk_graphs(c))) return rc;
   if (c->cfg.integrator == 0) {
     HIPCHK(launch_kick_drift(c->sp, c->d_inst, pbufs(c, c->cur), c->info[c->pcur],
-                             c->F[c->pcur], c->T[c->pcur], nullptr, c->stream));
+                             c->F[c->pcur], c->T[c->pcur], nullptr, c->d_clock,
+                             s0 + 1 - c->host_base, c->stream));
     int64_t s = s0 + 1;
     while (s <= s_end) {
       if (graphs && s % K == 0 && s + K - 1 <= s_end - 1) {
@@ -1898,7 +1926,7 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
     // translating walls: search again with the walls where they are at the
     // restored time (the lists were built with them elsewhere)
     {
-      if (int rc = enqueue_rebuild(c, 0, 1, 0)) return rc;
+      if (int rc = enqueue_rebuild(c, 0, 1, 0, next_eval_rel(c))) return rc;
       c->dyn_acc = 0.0;
       c->dyn_wacc = 0.0;
       int flags = 0;
@@ -1907,7 +1935,7 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
     }
   }
   HostSnapshot h;
-  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  if (int rc = snapshot(c, h, true, false, false)) return rc;
   const size_t n = (size_t)c->n;
   const int L = c->pcur;
   const Instance& In = c->inst[(size_t)instance];
@@ -1950,10 +1978,17 @@ int dem_restore(dem_ctx* c, int32_t instance, int64_t n_pairs, const int64_t* pa
       hs[e] = hs[(size_t)c->cap + e] = hs[2 * (size_t)c->cap + e] = 0.0;
     }
   }
+  // a pair that does not touch at the current positions keeps no history:
+  // the first force evaluation, here, would restart it at zero (and the row
+  // cuts of the force kernel may not read its entry until it can touch)
   auto set_entry = [&](int p, int q, double sgn, const double* d) -> bool {
     for (int k = 0; k < rl[(size_t)p]; ++k) {
       const size_t e = (size_t)nbr_entry(p, k, c->max_nb);
       if ((nb[e] & 0x7fffffff) != q) continue;
+      const double4 xp = h.pos[(size_t)p], xq = h.pos[(size_t)q];
+      const double dx = xq.x - xp.x, dy = xq.y - xp.y, dz = xq.z - xp.z;
+      const double rsum = xp.w + xq.w;
+      if (!(((dx * dx + dy * dy) + dz * dz) < rsum * rsum)) return true;
       nb[e] = q | (int)0x80000000u;
       for (int a = 0; a < 3; ++a) hs[(size_t)a * (size_t)c->cap + e] = sgn * d[a];
       return true;
@@ -2023,7 +2058,7 @@ int dem_restore_mesh_contacts(dem_ctx* c, int32_t instance, int64_t n_tri,
   }
   if (int rc = wait_user(c)) return rc;
   HostSnapshot h;
-  if (int rc = snapshot(c, h, false, false, false)) return rc;
+  if (int rc = snapshot(c, h, true, false, false)) return rc;
   const size_t n = (size_t)c->n;
   const int L = c->pcur;
   const Instance& In = c->inst[(size_t)instance];
@@ -2327,7 +2362,7 @@ int dem_resort(dem_ctx* c) {
   if (c->failed) return set_err(DEM_ESTATE, "a previous error is sticky");
   if (int rc = wait_user(c)) return rc;
   if (c->n == 0) return DEM_OK;
-  if (int rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base)) return rc;
+  if (int rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base, next_eval_rel(c))) return rc;
   c->dyn_acc = 0.0;
   c->dyn_wacc = 0.0;
   int flags = 0;
@@ -2391,7 +2426,7 @@ int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
   int64_t steps = 0;
   int rc = DEM_OK;
   auto forced_search = [&]() -> int {
-    int r = enqueue_rebuild(c, 0, 1, c->step - c->host_base);
+    int r = enqueue_rebuild(c, 0, 1, c->step - c->host_base, next_eval_rel(c));
     if (r) return r;
     int flags = 0;
     if ((r = read_flags(c, &flags))) return r;
@@ -2442,7 +2477,8 @@ int dem_autotune(dem_ctx* c, int32_t trial_steps, dem_tuning* out) {
     float total = 0.f;
     for (int r = 0; r < 3 && rc == DEM_OK; ++r) {
       hipError_t he = hipEventRecord(e0, c->stream);
-      if (he == hipSuccess && (rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base)) == DEM_OK) {
+      if (he == hipSuccess &&
+          (rc = enqueue_rebuild(c, 0, 1, c->step - c->host_base, next_eval_rel(c))) == DEM_OK) {
         he = hipEventRecord(e1, c->stream);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.f;

@@ -19,6 +19,11 @@ constexpr int kInstShift = 20;      // info bits 20..30: instance of the particl
 constexpr int kDriftSpread = 32;  // words per drift record
 constexpr int kMaxInstances = 2048;
 constexpr int kMaxMeshTriangles = 1 << 24;  // per instance
+// Particles per context: while the contact search builds a row, the top three
+// bits of each entry carry the pair's gap class, so sorted indices stay below
+// 2^29.
+constexpr int kClassShift = 29;
+constexpr int64_t kMaxParticles = (int64_t)1 << kClassShift;
 
 // Sticky error bits raised by kernels (read once per dem_step call).
 enum : int {
@@ -132,6 +137,18 @@ struct StepParams {
   uint32_t n_keys; // total cell keys; key n_keys collects inactive particles
   double drift_scale;  // dt * 2 / skin when every instance has the same skin,
                        // else 0 (then taken per particle from its instance)
+  // Displacement bound since the last contact search, in units of half the
+  // skin of each particle's instance, for the row cuts (see NbrList): the
+  // force evaluation at absolute step s (positions x^s) uses
+  // acc(s) = bacc[(s - 1) % 3] + sqrt(max of brec[s % 3]), where brec[s % 3]
+  // (kDriftSpread words, non-negative doubles as bits) holds the largest
+  // squared drift |v| dt (half skins) of the update that produced x^s.  The
+  // evaluation writes bacc[s % 3] = acc(s), raises brec[(s + 1) % 3] with
+  // its own update and clears brec[(s + 2) % 3]; a search at step s sets
+  // bacc[(s - 1) % 3] and brec[s % 3] to zero.  No particle has moved more
+  // than acc(s) half skins from where the last search saw it.
+  double* bacc;             // 3 words
+  unsigned long long* brec; // 3 * kDriftSpread words
 };
 
 // Particle arrays in sorted (spatial) order.  pos = (x, y, z, R),
@@ -146,12 +163,26 @@ struct ParticleBufs {
 // entry (i, k) lives at ((i / 64) * max_nb + k) * 64 + i % 64.  Bit 31 of a
 // neighbour index is set while the pair touches; the stored history of an
 // entry without bit 31 is undefined and stands for zero.
+//
+// A search orders each row by the gap g = d - (R_i + R_j) it found: the
+// touching pairs first, then the pairs with g < s/8, g < s/4, g < s/2 and the
+// rest (s the skin); rowcut packs the ends of the middle three groups (10
+// bits each, 1023 = the whole row).  Two particles that each moved at most
+// acc s/2 since the search come at most acc s closer, so while acc < f the
+// entries with g >= f s cannot touch and the force evaluation reads the row
+// only up to the matching end (f = 1/8, 1/4, 1/2).
 struct NbrList {
   int* nbr;      // sorted index of the neighbour
   double* hist;  // 3 planes of tangential overlap (x, y, z), stride cap
   int* rowlen;
   int64_t cap;   // entries per plane
+  int* rowcut;   // per particle: the three row cuts
 };
+
+// Gap classes of the row cuts: fractions of the skin.
+constexpr double kCutFrac[3] = {0.125, 0.25, 0.5};
+constexpr int kCutBits = 10;
+constexpr int kCutMask = (1 << kCutBits) - 1;  // a stored cut of 1023 means "the whole row"
 
 // Particle-wall slots: slot s of particle i at s * n + i.
 struct WallSlots {
@@ -180,6 +211,8 @@ hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint3
 // perm: new -> old index; inv receives old -> new
 // The particle-wall and particle-triangle searches take the walls where they
 // are at time (*clock + step_rel) dt.
+// It also restarts the displacement bound (StepParams) for the force
+// evaluation at step *clock + bound_step_rel.
 hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* perm, int* inv,
                           ParticleBufs src,
                           ParticleBufs dst, const int* gid_src, int* gid_dst,
@@ -187,11 +220,12 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           MeshTables mt, MeshSlots ms_src, MeshSlots ms_dst,
                           const double4* F_src, const double4* T_src, double4* F_dst,
-                          double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
-                          hipStream_t s);
-hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double4* pos,
-                         const int* info, const int* start, const int* perm, const int* inv,
-                         NbrList old_l, NbrList new_l, int* flags, hipStream_t s);
+                          double4* T_dst, const int64_t* clock, int64_t step_rel,
+                          int64_t bound_step_rel, int* flags, hipStream_t s);
+hipError_t launch_search(const InstDev* inst, int n_inst, const StepParams& sp,
+                         const double4* pos, const int* info, const int* start, const int* perm,
+                         const int* inv, NbrList old_l, NbrList new_l, int* flags,
+                         hipStream_t s);
 
 // force + integration kernels.  mode: 0 = velocity Verlet fused (second half
 // kick of this step, first half kick and drift of the next), 1 = velocity
@@ -223,9 +257,12 @@ hipError_t launch_mesh(int precision, const StepParams& sp, const PairCoef* pw,
 // largest squared drift |v| dt of the step, in units of half the particle's
 // skin (each wavefront raises one word: spreading the atomics over several
 // words keeps them from queueing on one address).
+// The kick and drift produce the positions of step *clock + step_rel, whose
+// displacement-bound record (StepParams) they raise.
 hipError_t launch_kick_drift(const StepParams& sp, const InstDev* inst, ParticleBufs st,
                              const int* info, const double4* F, const double4* T,
-                             unsigned long long* drift, hipStream_t s);
+                             unsigned long long* drift, const int64_t* clock, int64_t step_rel,
+                             hipStream_t s);
 hipError_t launch_tick(int64_t* clock, int64_t k, hipStream_t s);
 // statistics: out[0] active, [1] list entries, [2] touching entries, [3] wall slots
 hipError_t launch_stats(const StepParams& sp, const double4* pos, const int* info,

@@ -56,6 +56,14 @@ __device__ inline uint32_t cell_key(const GridDev& g, int cx, int cy, int cz) {
   return g.mort[0][cx] | g.mort[1][cy] | g.mort[2][cz];
 }
 
+// Slot of the displacement-bound ring (StepParams) for absolute step s + d
+// (s >= 0; 2^32 = 1 mod 3, so s mod 3 follows from its two 32-bit halves).
+__device__ __forceinline__ int bound_slot(int64_t s, int d) {
+  const uint64_t u = (uint64_t)s;
+  const uint32_t r = ((uint32_t)(u >> 32) % 3u + (uint32_t)u % 3u) % 3u;
+  return (int)((r + 3u + (uint32_t)d) % 3u);
+}
+
 // ------------------------------------------------------------------ fill
 
 __global__ void k_fill_i32(int* p, int v, int64_t n) {
@@ -449,9 +457,15 @@ __global__ void k_reorder(StepParams sp, const InstDev* __restrict__ inst,
                           const double4* __restrict__ F_src, const double4* __restrict__ T_src,
                           double4* __restrict__ F_dst, double4* __restrict__ T_dst,
                           const int64_t* __restrict__ clock, int64_t step_rel,
-                          int* __restrict__ flags) {
+                          int64_t bound_step_rel, int* __restrict__ flags) {
   int p = xcd_block() * kBlock + threadIdx.x;
   const int n = sp.n;
+  if (blockIdx.x == 0 && threadIdx.x < kDriftSpread) {
+    // the positions of the next force evaluation are where this search sees them
+    const int r = bound_slot(*clock + bound_step_rel, 0);
+    sp.brec[r * kDriftSpread + threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) sp.bacc[bound_slot(*clock + bound_step_rel, -1)] = 0.0;
+  }
   if (p >= n) return;
   const double t = (double)(*clock + step_rel) * sp.dt;  // walls where they are now
   int o = perm[p];
@@ -562,13 +576,13 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
                           WallSlots ws_src, WallSlots ws_dst, const WallDev* walls,
                           MeshTables mt, MeshSlots ms_src, MeshSlots ms_dst,
                           const double4* F_src, const double4* T_src, double4* F_dst,
-                          double4* T_dst, const int64_t* clock, int64_t step_rel, int* flags,
-                          hipStream_t s) {
-  if (sp.n <= 0) return hipSuccess;
+                          double4* T_dst, const int64_t* clock, int64_t step_rel,
+                          int64_t bound_step_rel, int* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_reorder, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, perm, inv,
                      src, dst,
                      gid_src, gid_dst, info_src, info_dst, xref, ws_src, ws_dst, walls, mt,
-                     ms_src, ms_dst, F_src, T_src, F_dst, T_dst, clock, step_rel, flags);
+                     ms_src, ms_dst, F_src, T_src, F_dst, T_dst, clock, step_rel,
+                     bound_step_rel, flags);
   return hipGetLastError();
 }
 
@@ -577,12 +591,10 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
 // Broad + fine search for particle p (sorted order): scan its own and the 26
 // surrounding cells and keep q != p with |x_q - x_p|^2 < r_s^2 (evaluated in
 // a fixed order without fused operations).  Pairs that touch now go to the
-// front of the row and the others behind them, so that during the next K
-// steps the history accesses of a wavefront stay in few cache lines.  Then
-// the tangential overlaps are carried over: every entry of p's old row that
-// was touching (bit 31) names its partner by old index; inv maps it to the new
-// index, which is looked up in the new row.  Entries without bit 31 have zero
-// history, which is therefore never stored.
+// front of the row (during the next steps the
+// history accesses of a wavefront then stay in few cache lines), the others
+// behind them in the order of their gap class (the row cuts of NbrList).
+// Then the tangential overlaps are carried over (below).
 // Positions of the search block's own sorted particles, staged in LDS: the
 // cells around a block's particles hold many of the block's particles (a
 // window with a halo of further sorted neighbours measured slower, its LDS
@@ -604,7 +616,88 @@ struct SearchTile {
   }
 };
 
-__global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
+// Gap class of a candidate pair at distance^2 d2 (radius sum rsum, skin sk):
+// 0 touching, 1..3 gap d - rsum below kCutFrac[0..2] skins, 4 farther
+// (compared as squares, so no square root; the force evaluation keeps a
+// relative margin far above the rounding of these comparisons).
+__device__ __forceinline__ int gap_class(double d2, double rsum, double sk) {
+  const double a = rsum + kCutFrac[0] * sk, b = rsum + kCutFrac[1] * sk,
+               c = rsum + kCutFrac[2] * sk;
+  return d2 < rsum * rsum ? 0 : (d2 < a * a ? 1 : (d2 < b * b ? 2 : (d2 < c * c ? 3 : 4)));
+}
+
+// Five counters, one per gap class, kept in registers (an array indexed by a
+// class would be placed in memory).
+struct Five {
+  int v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0;
+  __device__ __forceinline__ int get(int i) const {
+    return i == 0 ? v0 : (i == 1 ? v1 : (i == 2 ? v2 : (i == 3 ? v3 : v4)));
+  }
+  __device__ __forceinline__ void bump(int i) {
+    v0 += i == 0 ? 1 : 0;
+    v1 += i == 1 ? 1 : 0;
+    v2 += i == 2 ? 1 : 0;
+    v3 += i == 3 ? 1 : 0;
+    v4 += i == 4 ? 1 : 0;
+  }
+  __device__ __forceinline__ void set(int i, int x) {
+    v0 = i == 0 ? x : v0;
+    v1 = i == 1 ? x : v1;
+    v2 = i == 2 ? x : v2;
+    v3 = i == 3 ? x : v3;
+    v4 = i == 4 ? x : v4;
+  }
+};
+
+constexpr unsigned kRowIndexMask = (1u << kClassShift) - 1u;
+
+// A row under construction in the contact search: its first kRowLds entries
+// in the workgroup's LDS (column threadIdx.x, so the lanes of a wavefront
+// always hit distinct banks), the rest in place in the neighbour list.
+constexpr int kRowLds = 11;
+constexpr int kCarryBatch = 4;
+struct BuildRow {
+  int* lds;  // &buf[0][threadIdx.x], stride kBlock
+  int* nbr;
+  int p, max_nb;
+  __device__ __forceinline__ unsigned load(int t) const {
+    return t < kRowLds ? (unsigned)lds[t * kBlock] : (unsigned)nbr[nbr_entry(p, t, max_nb)];
+  }
+  __device__ __forceinline__ void store(int t, unsigned v) const {
+    if (t < kRowLds)
+      lds[t * kBlock] = (int)v;
+    else
+      nbr[nbr_entry(p, t, max_nb)] = (int)v;
+  }
+};
+
+// One class of the in-place row sort (below): fill the free slots of class C
+// in order; an entry found in one of them that belongs to class k != C goes
+// to the next free slot of class k, whose occupant moves on in turn, until
+// an entry of class C comes back for the slot.
+template <int C>
+__device__ __forceinline__ void place_class(const BuildRow& row, Five& nx, const Five& en) {
+  for (int t = nx.get(C); t < en.get(C); ++t) {
+    unsigned v = row.load(t);
+    int k = (int)(v >> kClassShift);
+    while (k != C) {
+      const int u = nx.get(k);
+      nx.bump(k);
+      const unsigned f = row.load(u);
+      row.store(u, v & kRowIndexMask);
+      v = f;
+      k = (int)(v >> kClassShift);
+    }
+    row.store(t, v & kRowIndexMask);
+  }
+  nx.set(C, en.get(C));
+}
+
+// kOne: the batch has a single instance, whose table entry then sits in
+// scalar registers.
+template <bool kOne>
+__global__ void __launch_bounds__(kBlock)
+k_search(const InstDev* __restrict__ inst, StepParams sp,
                          const double4* __restrict__ pos,
                          const int* __restrict__ info, const int* __restrict__ start,
                          const int* __restrict__ perm, const int* __restrict__ inv,
@@ -612,6 +705,7 @@ __global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
   const int b0 = xcd_block() * kBlock;
   int p = b0 + threadIdx.x;
   __shared__ SearchTile tile;
+  __shared__ int rowbuf[kRowLds][kBlock];
   tile.stage(pos, b0, sp.n);
   __syncthreads();
   if (p >= sp.n) return;
@@ -619,19 +713,22 @@ __global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
   const int inf = info[p];
   if (inf & kInactive) {
     new_l.rowlen[p] = 0;
+    new_l.rowcut[p] = 0;
     return;
   }
-  const InstDev& I = inst[inf >> kInstShift];
+  const BuildRow row{&rowbuf[0][threadIdx.x], new_l.nbr, p, max_nb};
+  const InstDev& I = inst[kOne ? 0 : inf >> kInstShift];
   const GridDev& g = I.grid;
   const double rs2 = I.rs2;
+  const double sk = I.skin;
   const uint32_t kbase = I.key_base;
   const double4 pp = pos[p];
   const int cx = cell_coord(pp.x, g.lo[0], g.h, g.nc[0]);
   const int cy = cell_coord(pp.y, g.lo[1], g.h, g.nc[1]);
   const int cz = cell_coord(pp.z, g.lo[2], g.h, g.nc[2]);
-  int front = 0;  // touching pairs fill slots 0, 1, ...
-  int back = 0;   // the others fill slots max_nb-1, max_nb-2, ...
-  bool overflow = false;
+  // one pass: every candidate is stored in the order found, its gap class in
+  // the entry's top bits
+  int len = 0;
   for (int dz = -1; dz <= 1; ++dz) {
     const int z = cz + dz;
     if (z < 0 || z >= g.nc[2]) continue;
@@ -650,53 +747,113 @@ __global__ void k_search(const InstDev* __restrict__ inst, StepParams sp,
           const double ddx = pq.x - pp.x, ddy = pq.y - pp.y, ddz = pq.z - pp.z;
           const double d2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
           if (!(d2 < rs2)) continue;
-          if (front + back == max_nb) {
-            overflow = true;
-            continue;
-          }
-          const double rsum = pp.w + pq.w;
-          const int slot = d2 < rsum * rsum ? front++ : max_nb - 1 - back++;
-          new_l.nbr[nbr_entry(p, slot, max_nb)] = q;
+          const int c = gap_class(d2, pp.w + pq.w, sk);
+          if (len < max_nb) row.store(len, (unsigned)q | ((unsigned)c << kClassShift));
+          ++len;
         }
       }
     }
   }
-  // close the gap: the non-touching entries follow the touching ones
-  for (int b = 0; b < back; ++b) {
-    const int64_t from = nbr_entry(p, max_nb - 1 - b, max_nb);
-    const int64_t to = nbr_entry(p, front + b, max_nb);
-    if (from != to) new_l.nbr[to] = new_l.nbr[from];
+  int front = 0;
+  int cut = (kCutMask << (2 * kCutBits)) | (kCutMask << kCutBits) | kCutMask;
+  if (len > max_nb) {
+    // the row is incomplete and the step fails; leave valid indices behind
+    atomicOr(flags, kFlagNbrOverflow);
+    len = max_nb;
+    for (int k = 0; k < len; ++k) row.store(k, row.load(k) & kRowIndexMask);
+  } else {
+    // sort the row by class in place (each entry moves once), clearing the
+    // class bits
+    Five at;
+    for (int t = 0; t < len; ++t) at.bump((int)(row.load(t) >> kClassShift));
+    Five nx, en;
+    nx.v0 = 0;
+    en.v0 = nx.v1 = at.v0;
+    en.v1 = nx.v2 = en.v0 + at.v1;
+    en.v2 = nx.v3 = en.v1 + at.v2;
+    en.v3 = nx.v4 = en.v2 + at.v3;
+    en.v4 = len;
+    place_class<0>(row, nx, en);
+    place_class<1>(row, nx, en);
+    place_class<2>(row, nx, en);
+    place_class<3>(row, nx, en);
+    for (int t = nx.v4; t < len; ++t) row.store(t, row.load(t) & kRowIndexMask);
+    front = at.v0;
+    const int c1 = en.v1 < kCutMask ? en.v1 : kCutMask;
+    const int c2 = en.v2 < kCutMask ? en.v2 : kCutMask;
+    const int c3 = en.v3 < kCutMask ? en.v3 : kCutMask;
+    cut = c1 | (c2 << kCutBits) | (c3 << (2 * kCutBits));
   }
-  const int len = front + back;
   new_l.rowlen[p] = len;
-  if (overflow) atomicOr(flags, kFlagNbrOverflow);
-  // history carry-over for pairs touching at the last force evaluation
+  new_l.rowcut[p] = cut;
+  // history carry-over for pairs that touched at the last force evaluation
+  // and touch now (a pair that does not touch now has its overlap restarted
+  // at zero by the first evaluation, at these positions, anyway): every entry
+  // of p's old row with bit 31 names its partner by old index; inv maps it to
+  // the new index, which is looked up among the touching entries of the new
+  // row.  Entries without bit 31 have zero history, which is never stored.
+  // The old entries, their inverse-permutation lookups and the histories of
+  // the matched pairs are fetched kCarryBatch entries at a time, so that
+  // their loads are in flight together.
   const int op = perm[p];
   const int olen = old_l.rowlen[op];
-  for (int k = 0; k < olen; ++k) {
-    const int64_t oe = nbr_entry(op, k, max_nb);
-    const int ojr = old_l.nbr[oe];
-    if (!(ojr & (int)0x80000000u)) continue;
-    const int q = inv[ojr & 0x7fffffff];
-    for (int m = 0; m < len; ++m) {
-      const int64_t ne = nbr_entry(p, m, max_nb);
-      if (new_l.nbr[ne] == q) {
-        new_l.nbr[ne] = q | (int)0x80000000u;
-        new_l.hist[ne] = old_l.hist[oe];
-        new_l.hist[new_l.cap + ne] = old_l.hist[old_l.cap + oe];
-        new_l.hist[2 * new_l.cap + ne] = old_l.hist[2 * old_l.cap + oe];
-        break;
+  for (int k0 = 0; k0 < olen; k0 += kCarryBatch) {
+    int oj[kCarryBatch], qn[kCarryBatch];
+#pragma unroll
+    for (int j = 0; j < kCarryBatch; ++j)
+      oj[j] = k0 + j < olen ? old_l.nbr[nbr_entry(op, k0 + j, max_nb)] : 0;
+#pragma unroll
+    for (int j = 0; j < kCarryBatch; ++j)
+      qn[j] = (oj[j] & (int)0x80000000u) ? inv[oj[j] & 0x7fffffff] : -1;
+    int mj[kCarryBatch];
+#pragma unroll
+    for (int j = 0; j < kCarryBatch; ++j) {
+      mj[j] = -1;
+      if (qn[j] < 0) continue;
+      const unsigned q = (unsigned)qn[j];
+      for (int m = 0; m < front; ++m) {
+        if (row.load(m) == q) {
+          row.store(m, q | 0x80000000u);
+          mj[j] = m;
+          break;
+        }
       }
     }
+    double h0[kCarryBatch], h1[kCarryBatch], h2[kCarryBatch];
+#pragma unroll
+    for (int j = 0; j < kCarryBatch; ++j) {
+      if (mj[j] < 0) continue;
+      const int64_t oe = nbr_entry(op, k0 + j, max_nb);
+      h0[j] = old_l.hist[oe];
+      h1[j] = old_l.hist[old_l.cap + oe];
+      h2[j] = old_l.hist[2 * old_l.cap + oe];
+    }
+#pragma unroll
+    for (int j = 0; j < kCarryBatch; ++j) {
+      if (mj[j] < 0) continue;
+      const int64_t ne = nbr_entry(p, mj[j], max_nb);
+      new_l.hist[ne] = h0[j];
+      new_l.hist[new_l.cap + ne] = h1[j];
+      new_l.hist[2 * new_l.cap + ne] = h2[j];
+    }
   }
+  // the part of the row held in LDS goes out entry by entry for the whole
+  // wavefront at once (whole cache lines; the part beyond is in place)
+  for (int k = 0; k < kRowLds; ++k)
+    if (k < len) new_l.nbr[nbr_entry(p, k, max_nb)] = rowbuf[k][threadIdx.x];
 }
 
-hipError_t launch_search(const InstDev* inst, const StepParams& sp, const double4* pos,
-                         const int* info, const int* start, const int* perm, const int* inv,
-                         NbrList old_l, NbrList new_l, int* flags, hipStream_t s) {
+hipError_t launch_search(const InstDev* inst, int n_inst, const StepParams& sp,
+                         const double4* pos, const int* info, const int* start, const int* perm,
+                         const int* inv, NbrList old_l, NbrList new_l, int* flags,
+                         hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_search, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos, info,
-                     start, perm, inv, old_l, new_l, flags);
+  if (n_inst == 1)
+    hipLaunchKernelGGL(k_search<true>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos,
+                       info, start, perm, inv, old_l, new_l, flags);
+  else
+    hipLaunchKernelGGL(k_search<false>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos,
+                       info, start, perm, inv, old_l, new_l, flags);
   return hipGetLastError();
 }
 
@@ -1221,13 +1378,19 @@ __device__ __forceinline__ double force_particle(
 // one of kDriftSpread words: non-negative doubles order like their bit
 // patterns.  Every lane of the wavefront calls it; waves_per_block is the
 // block size in wavefronts.
-__device__ __forceinline__ void wave_max_to(unsigned long long* dst, double v,
-                                            int waves_per_block = kBlock / 64) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+__device__ __forceinline__ void wave_max_store(unsigned long long* dst, double v,
+                                               int waves_per_block = kBlock / 64) {
   const int w = (blockIdx.x * waves_per_block + (threadIdx.x >> 6)) & (kDriftSpread - 1);
   if ((threadIdx.x & 63) == 0 && v > 0.0)
     atomicMax(dst + w, (unsigned long long)__double_as_longlong(v));
+}
+// returns the wavefront's maximum
+__device__ __forceinline__ double wave_max_to(unsigned long long* dst, double v,
+                                              int waves_per_block = kBlock / 64) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  wave_max_store(dst, v, waves_per_block);
+  return v;
 }
 
 // Occupancy floor: four wavefronts per SIMD (128 VGPRs, no spills), except
@@ -1247,12 +1410,41 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
         const double4* __restrict__ Tx, double* __restrict__ pf) {
   const int b0 = xcd_block() * BS;
   const int i = b0 + threadIdx.x;
-  // the row length and the first row entry do not depend on the tile: their
-  // loads are issued before it is staged (entry 0 exists for every row)
-  int len = 0, jr0 = 0;
+  const int64_t step = *clock + step_rel;  // these positions are x^step
+  // the row length, its cuts and the first row entry do not depend on the
+  // tile: their loads are issued before it is staged (entry 0 exists for
+  // every row)
+  int len = 0, cut = 0, jr0 = 0;
   if (i < sp.n) {
     len = ld_own(l.rowlen + i);
+    cut = ld_own(l.rowcut + i);
     jr0 = ld_own(l.nbr + nbr_entry(i, 0, sp.max_nb));
+  }
+  // displacement bound of x^step since the last search (half skins): the
+  // previous evaluation's bound plus the largest drift of the update since;
+  // then the row cut it allows (uniform across the wavefront; a relative
+  // margin of 1e-6 covers every rounding of the bound and of the gaps)
+  int u_cut;
+  {
+    // the record's words, read with one address for the whole wavefront
+    // (non-negative doubles order like their bit patterns)
+    const unsigned long long* rw = sp.brec + bound_slot(step, 0) * kDriftSpread;
+    unsigned long long mb = 0ull;
+#pragma unroll
+    for (int w = 0; w < kDriftSpread; ++w) mb = rw[w] > mb ? rw[w] : mb;
+    const double m2 = __longlong_as_double((long long)mb);
+    const double acc = sp.bacc[bound_slot(step, -1)] + sqrt(m2);
+    if (blockIdx.x == 0 && threadIdx.x < kDriftSpread) {
+      sp.brec[bound_slot(step, 2) * kDriftSpread + threadIdx.x] = 0ull;
+      if (threadIdx.x == 0) sp.bacc[bound_slot(step, 0)] = acc;
+    }
+    const double accm = acc * (1.0 + 1e-6);
+    u_cut = accm < kCutFrac[0] ? 0 : (accm < kCutFrac[1] ? 1 : (accm < kCutFrac[2] ? 2 : 3));
+    u_cut = __builtin_amdgcn_readfirstlane(u_cut);
+  }
+  if (u_cut < 3) {
+    const int c = (cut >> (kCutBits * u_cut)) & kCutMask;
+    if (c != kCutMask && c < len) len = c;
   }
   __shared__ Tile<BS> tile;
   tile.stage(in, info, b0, sp.n);
@@ -1260,9 +1452,13 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   double d = 0.0;
   if (i < sp.n)
     d = force_particle<R, MODE, MODEL, REC>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
-                                       To, clock, step_rel, flags, drift != nullptr, xsel, Fx,
+                                       To, clock, step_rel, flags, MODE != 1, xsel, Fx,
                                        Tx, tile, len, jr0, pf);
-  if (drift) wave_max_to(drift, d, BS / 64);
+  if (MODE != 1) {
+    // this launch's own update produced x^(step + 1)
+    const double dm = wave_max_to(sp.brec + bound_slot(step, 1) * kDriftSpread, d, BS / 64);
+    if (drift) wave_max_store(drift, dm, BS / 64);
+  }
 }
 
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
@@ -1501,19 +1697,24 @@ __device__ __forceinline__ double kick_drift_one(int i, const StepParams& sp, co
 __global__ void k_kick_drift(StepParams sp, const InstDev* __restrict__ inst, ParticleBufs st,
                              const int* __restrict__ info, const double4* __restrict__ F,
                              const double4* __restrict__ T,
-                             unsigned long long* __restrict__ drift) {
+                             unsigned long long* __restrict__ drift,
+                             const int64_t* __restrict__ clock, int64_t step_rel) {
   int i = xcd_block() * kBlock + threadIdx.x;
   double d = 0.0;
-  if (i < sp.n && !(info[i] & kInactive)) d = kick_drift_one(i, sp, inst, st, info, F, T, drift != nullptr);
-  if (drift) wave_max_to(drift, d);
+  if (i < sp.n && !(info[i] & kInactive)) d = kick_drift_one(i, sp, inst, st, info, F, T, true);
+  // the displacement bound's record of the update that produced x^step
+  const int64_t step = *clock + step_rel;
+  const double dm = wave_max_to(sp.brec + bound_slot(step, 0) * kDriftSpread, d);
+  if (drift) wave_max_store(drift, dm);
 }
 
 hipError_t launch_kick_drift(const StepParams& sp, const InstDev* inst, ParticleBufs st,
                              const int* info, const double4* F, const double4* T,
-                             unsigned long long* drift, hipStream_t s) {
+                             unsigned long long* drift, const int64_t* clock, int64_t step_rel,
+                             hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, sp, inst, st, info,
-                     F, T, drift);
+                     F, T, drift, clock, step_rel);
   return hipGetLastError();
 }
 
