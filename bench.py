@@ -503,7 +503,7 @@ def cpu_baseline(args, scene, settled, precs):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000, help="timed steps per leg")
+    ap.add_argument("--steps", type=int, default=5000, help="timed steps per leg")
     ap.add_argument("--warmup", type=int, default=200,
                     help="untimed steps right before each timed window (after settling)")
     ap.add_argument("--settle", type=int, default=20000,
@@ -539,7 +539,7 @@ def main():
     ap.add_argument("--dam-n", type=int, default=1_280_000)
     ap.add_argument("--dam-steps", type=int, default=4000,
                     help="steps with the dam standing, then timed steps after its removal")
-    ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--batch-steps", type=int, default=20000)
     ap.add_argument("--batch-settle", type=int, default=10000,
                     help="untimed settling steps of the batch of drums")
     ap.add_argument("--calibrate-copy", action="store_true",
