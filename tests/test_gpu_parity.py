@@ -441,7 +441,10 @@ def test_drum_1m_settled_forces_one_step_both_precisions(Dem):
             # terms cancel (1.2e-9 on this bed); the term scale does not
             assert ef_net <= 1e-8 and ef <= 1e-10 and et <= 1e-10
         else:
-            assert ef <= 1e-5 and et <= 1e-5
+            # against the net scale the FP32 rounding of each of two cancelling
+            # terms shows (9.7e-4 to 3.9e-3 measured on this bed): a ceiling
+            # near it
+            assert ef <= 1e-5 and et <= 1e-5 and ef_net <= 1e-2
 
 
 # ------------------------------------------------------- dynamic search trigger

@@ -17,6 +17,12 @@ from oracle import oracle_from_scene
 
 pytestmark = pytest.mark.gpu
 
+# FP32 law against the oracle's net contact-force scale after one step from a
+# common start (where spring and dashpot nearly cancel, the FP32 rounding of
+# each term shows; measured 1.6e-5 on the dense hopper fill, 9.5e-6 on the
+# wedge silo): a ceiling a few times above that
+NET32_CEILING = 1e-4
+
 
 @pytest.fixture(scope="module")
 def Dem():
@@ -138,15 +144,19 @@ def test_full_hopper_silo_initial_sets_bit_exact(Dem):
                        (np.linalg.norm(To, axis=1) + S2 * R + 1e-300)))
 
     ef64, et64 = term_err(*g64.get_forces())
-    ef32, et32 = term_err(*g.get_forces())
+    F32, T32 = g.get_forces()
+    ef32, et32 = term_err(F32, T32)
+    ef32n = np.max(np.linalg.norm(F32 - Fo, axis=1) / (np.linalg.norm(Fo, axis=1) + S + 1e-300))
     nt = int(o.contacts()[2].sum())
     print("dense fill, step 1: touching", nt, "fp64 net", ef, et, "term scale", ef64, et64,
-          "fp32 (term scale)", ef32, et32, flush=True)
+          "fp32 (term scale)", ef32, et32, "fp32 forces (net scale)", ef32n, flush=True)
     assert nt > 500_000
     # the net scale amplifies last-bit differences where spring and dashpot
     # cancel; the term scale does not
     assert ef <= 1e-8 and et <= 1e-8 and ef64 <= 1e-10 and et64 <= 1e-10
     assert ef32 <= 1e-5 and et32 <= 1e-5
+    # against the net scale the FP32 rounding of cancelling terms shows
+    assert ef32n <= NET32_CEILING
     sets_equal(g, o)
 
 
@@ -181,13 +191,15 @@ def test_full_wedge_silo_parity(Dem):
         F32, T32 = g32.get_forces()
         ef32 = np.max(np.linalg.norm(F32 - Fo, axis=1) /
                       (np.linalg.norm(Fo, axis=1) + S2 + 1e-300))
+        ef32n = np.max(np.linalg.norm(F32 - Fo, axis=1) /
+                       (np.linalg.norm(Fo, axis=1) + S + 1e-300))
         et32 = np.max(np.linalg.norm(T32 - To, axis=1) /
                       (np.linalg.norm(To, axis=1) + S2 * R + 1e-300))
         print("step", g64.get_stats()["step"], "touching", nt, "wall", nw, "fp64", ef, et,
-              "fp32 (term scale)", ef32, et32, flush=True)
+              "fp32 (term scale)", ef32, et32, "fp32 forces (net scale)", ef32n, flush=True)
         assert nt > 20_000 and nw > 100
         assert ef <= 1e-9 and et <= 1e-9
         if steps == 1:
-            assert ef32 <= 1e-5 and et32 <= 1e-5
+            assert ef32 <= 1e-5 and et32 <= 1e-5 and ef32n <= NET32_CEILING
         sets_equal(g32, o)
     assert g64.get_stats()["n_active"] == n
