@@ -114,6 +114,7 @@ struct dem_ctx {
   double4 *Fm = nullptr, *Tm = nullptr;
   // per-contact force record (tests): three planes of cap doubles, or null
   bool record_pf = false;
+  int pair_mode = 0;  // 1: one instance, every particle of type 0; 2: every particle of type 0
   double* pair_force = nullptr;
   std::vector<int> tri_wall, tri_local;  // per global triangle: instance wall, index in it
   int* nbr[2]{};
@@ -366,7 +367,7 @@ int enqueue_force(dem_ctx* c, int mode, int64_t step_rel, unsigned long long* dr
                       pbufs(c, a),
                       pbufs(c, a ^ 1), c->info[p], nlist(c, p), wslots(c, p), c->F[p], c->T[p],
                       c->d_clock, step_rel, c->d_flags, drift, c->has_mesh ? c->mtri[p] : nullptr,
-                      c->Fm, c->Tm, c->pair_force, c->force_block, c->stream));
+                      c->Fm, c->Tm, c->pair_force, c->force_block, c->pair_mode, c->stream));
   c->cur ^= 1;
   return DEM_OK;
 }
@@ -1211,6 +1212,10 @@ int commit(dem_ctx* c) {
 
   // packed particle state (1/m and 1/I are stored: the law needs 1/m_i + 1/m_j)
   std::vector<double4> hpos(NN), hvel(NN), homg(NN);
+  bool all_type0 = true;
+  for (const Instance& I : c->inst)
+    for (int32_t t : I.type) all_type0 = all_type0 && t == 0;
+  c->pair_mode = all_type0 ? (B == 1 ? 1 : 2) : 0;
   std::vector<int> hgid(NN), hinfo(NN);
   int64_t q = 0;
   for (int b = 0; b < B; ++b) {

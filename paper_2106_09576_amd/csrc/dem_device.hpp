@@ -236,6 +236,9 @@ hipError_t launch_search(const InstDev* inst, int n_inst, const StepParams& sp,
 // xsel is the first mesh candidate slot).  pf (may be null): the force of
 // every touching pair on the row's particle is also written to entry (i, k)
 // of three planes of l.cap doubles (a per-contact record for tests).
+// pair_mode: 1 when the batch is one instance whose particles all have type
+// 0 (every particle pair takes the pair table's first entry), 2 when every
+// particle has type 0 (the first entry of the particle's own row), else 0.
 hipError_t launch_force(int mode, int precision, const StepParams& sp, const InstDev* inst,
                         const PairCoef* pp,
                         const PairCoef* pw, const WallDev* walls, ParticleBufs in,
@@ -243,7 +246,7 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
                         const int* flags, unsigned long long* drift, const int* xsel,
                         const double4* Fx, const double4* Tx, double* pf, int block,
-                        hipStream_t s);
+                        int pair_mode, hipStream_t s);
 // Contacts of the particles with triangle candidates at time (*clock +
 // step_rel) dt (tangential overlaps updated): their force and torque into
 // Fm / Tm (written for those particles only).

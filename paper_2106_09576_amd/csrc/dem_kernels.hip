@@ -1202,7 +1202,7 @@ __device__ __forceinline__ double drift_scale(const StepParams& sp,
 // Forces on particle i and its integration; returns the squared drift of
 // this step in units of half the instance's skin (for the dynamic search
 // trigger) when asked for it.
-template <typename R, int MODE, int MODEL, bool REC, typename TileT>
+template <typename R, int MODE, int MODEL, bool REC, int PAIRS, typename TileT>
 __device__ __forceinline__ double force_particle(
     const int i, const StepParams& sp, const InstDev* __restrict__ inst,
     const PairCoef* __restrict__ ppc, const PairCoef* __restrict__ pwc,
@@ -1214,14 +1214,15 @@ __device__ __forceinline__ double force_particle(
     const int len, const int jr0, double* __restrict__ pf) {
   const int n = sp.n;
   double4 xi = tile.pos(in, i);
-  double4 vi = tile.vel(in, i);
-  double4 wi = tile.omg(in, i);
+  // the particle's own velocity and spin stay in the LDS tile during the row
+  // walk and are read where they are used (registers for the neighbour's)
+  const int own = i - tile.lo;
   const int inf = tile.info(info, i);
   // frozen after an error, and for inactive particles: carry the state over
   if ((inf & kInactive) || *flags != 0) {
     out.pos[i] = xi;
-    out.vel[i] = vi;
-    out.omg[i] = wi;
+    out.vel[i] = tile.v[own];
+    out.omg[i] = tile.w[own];
     if (MODE != 0) {
       Fo[i] = make_double4(0.0, 0.0, 0.0, 0.0);
       To[i] = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1234,6 +1235,12 @@ __device__ __forceinline__ double force_particle(
   const int row = ((inf >> kInstShift) * kMaxTypes + ti) * kMaxTypes;
   const PairCoef* __restrict__ ppi = ppc + row;
   const PairCoef* __restrict__ pwi = pwc + row;
+  // PAIRS 1: a single instance whose particles all have type 0, so every
+  // pair takes the table's first entry, read once for the wavefront;
+  // PAIRS 2: every particle has type 0, so the pair's entry is the first of
+  // the particle's own row and its load does not wait for the neighbour's
+  PairCoef pc0;
+  if (PAIRS == 1) pc0 = ppc[0];
   const double dt = sp.dt;
   double F[3] = {0.0, 0.0, 0.0};
   double T[3] = {0.0, 0.0, 0.0};
@@ -1263,9 +1270,19 @@ __device__ __forceinline__ double force_particle(
     if (d2 < rsum * rsum) {
       const double4 vj = tile.vel(in, j);
       const double4 wj = tile.omg(in, j);
-      const int tj = tile.info(info, j) & kTypeMask;
+      int oi = own;
+      asm volatile("" : "+v"(oi));  // keeps the LDS reads inside the loop
+      const double4 vi = tile.v[oi];
+      const double4 wi = tile.w[oi];
       double Fi[3], Mi[3];
-      pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      if (PAIRS == 1) {
+        pp_contact<R>(pc0, sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      } else if (PAIRS == 2) {
+        pp_contact<R>(ppi[0], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      } else {
+        const int tj = tile.info(info, j) & kTypeMask;
+        pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+      }
       st_own(dtl[0], l.hist + e);
       st_own(dtl[1], l.hist + cap + e);
       st_own(dtl[2], l.hist + 2 * cap + e);
@@ -1288,6 +1305,8 @@ __device__ __forceinline__ double force_particle(
       st_own(j, l.nbr + e);
     }
   }
+  double4 vi = tile.v[own];
+  double4 wi = tile.w[own];
   // walls: time of this force evaluation
   const double t = (double)(*clock + step_rel) * dt;
   for (int s = 0; s < kWallSlots; ++s) {
@@ -1398,7 +1417,8 @@ __device__ __forceinline__ double wave_max_to(unsigned long long* dst, double v,
 // three.
 // REC: also write every touching pair's force to pf (the per-contact record;
 // a separate instantiation, so the record costs the plain kernel nothing).
-template <typename R, int MODE, int MODEL, int BS, bool REC>
+// PAIRS: how a pair finds its material-pair constants (see force_particle).
+template <typename R, int MODE, int MODEL, int BS, bool REC, int PAIRS>
 __global__ void __launch_bounds__(BS)
     __attribute__((amdgpu_waves_per_eu(MODE == 2 && MODEL == 1 ? 3 : 4)))
 k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restrict__ ppc,
@@ -1451,9 +1471,9 @@ k_force(StepParams sp, const InstDev* __restrict__ inst, const PairCoef* __restr
   __syncthreads();
   double d = 0.0;
   if (i < sp.n)
-    d = force_particle<R, MODE, MODEL, REC>(i, sp, inst, ppc, pwc, walls, in, out, info, l, ws, Fo,
-                                       To, clock, step_rel, flags, MODE != 1, xsel, Fx,
-                                       Tx, tile, len, jr0, pf);
+    d = force_particle<R, MODE, MODEL, REC, PAIRS>(i, sp, inst, ppc, pwc, walls, in, out, info,
+                                                  l, ws, Fo, To, clock, step_rel, flags,
+                                                  MODE != 1, xsel, Fx, Tx, tile, len, jr0, pf);
   if (MODE != 1) {
     // this launch's own update produced x^(step + 1)
     const double dm = wave_max_to(sp.brec + bound_slot(step, 1) * kDriftSpread, d, BS / 64);
@@ -1468,29 +1488,31 @@ hipError_t launch_force(int mode, int precision, const StepParams& sp, const Ins
                         double4* F, double4* T, const int64_t* clock, int64_t step_rel,
                         const int* flags, unsigned long long* drift, const int* xsel,
                         const double4* Fx, const double4* Tx, double* pf, int block,
-                        hipStream_t s) {
+                        int pair_mode, hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
   dim3 gr(grid_for(sp.n, block)), bl(block);
-#define DEM_LAUNCH_REC(RT, M, L, REC)                                                          \
+#define DEM_LAUNCH_REC(RT, M, L, REC, PAIRS)                                                    \
   do {                                                                                          \
     if (block == 64)                                                                            \
-      hipLaunchKernelGGL((k_force<RT, M, L, 64, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,   \
-                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
-                         Tx, pf);                                                               \
+      hipLaunchKernelGGL((k_force<RT, M, L, 64, REC, PAIRS>), gr, bl, 0, s, sp, inst, pp, pw,   \
+                         walls, in, out, info, l, ws, F, T, clock, step_rel, flags, drift,      \
+                         xsel, Fx, Tx, pf);                                                     \
     else if (block == 128)                                                                      \
-      hipLaunchKernelGGL((k_force<RT, M, L, 128, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,  \
-                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
-                         Tx, pf);                                                               \
+      hipLaunchKernelGGL((k_force<RT, M, L, 128, REC, PAIRS>), gr, bl, 0, s, sp, inst, pp, pw,  \
+                         walls, in, out, info, l, ws, F, T, clock, step_rel, flags, drift,      \
+                         xsel, Fx, Tx, pf);                                                     \
     else                                                                                        \
-      hipLaunchKernelGGL((k_force<RT, M, L, 256, REC>), gr, bl, 0, s, sp, inst, pp, pw, walls,  \
-                         in, out, info, l, ws, F, T, clock, step_rel, flags, drift, xsel, Fx,   \
-                         Tx, pf);                                                               \
+      hipLaunchKernelGGL((k_force<RT, M, L, 256, REC, PAIRS>), gr, bl, 0, s, sp, inst, pp, pw,  \
+                         walls, in, out, info, l, ws, F, T, clock, step_rel, flags, drift,      \
+                         xsel, Fx, Tx, pf);                                                     \
   } while (0)
-#define DEM_LAUNCH(RT, M, L)                         \
-  do {                                               \
-    if (pf) DEM_LAUNCH_REC(RT, M, L, true);          \
-    else DEM_LAUNCH_REC(RT, M, L, false);            \
+#define DEM_LAUNCH(RT, M, L)                                     \
+  do {                                                           \
+    if (pf) DEM_LAUNCH_REC(RT, M, L, true, 0);                   \
+    else if (pair_mode == 1) DEM_LAUNCH_REC(RT, M, L, false, 1); \
+    else if (pair_mode == 2) DEM_LAUNCH_REC(RT, M, L, false, 2); \
+    else DEM_LAUNCH_REC(RT, M, L, false, 0);                     \
   } while (0)
 #define DEM_LAUNCH_MODE(RT, L)                \
   do {                                        \
