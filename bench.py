@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # per unordered candidate pair 8 B identity + 24 B history read + 24 B written
 BYTES_PER_PARTICLE = 152.0
 BYTES_PER_PAIR = 56.0
-MAIN_FORCE_BLOCK = 64
+MAIN_FORCE_BLOCK = 256
 
 
 def log(msg):
@@ -296,7 +296,7 @@ def measure_silos(args, precs):
     workload's time step with the plug gone; after the warmup steps the
     discharge is timed (spheres leaving the domain below the outlet become
     inactive; the rate counts active particle-steps).  Dynamic search,
-    64-thread force workgroups."""
+    256-thread force workgroups."""
     import numpy as np
     import workloads as W
     from paper_2106_09576_amd import Dem
@@ -572,7 +572,7 @@ def main():
     geo = scene["geometry"]
     precs = ["fp64", "fp32"] if args.precision == "both" else [args.precision]
     # the settings dem_autotune picks for this workload, fixed so that the
-    # headline run is reproducible: displacement-triggered search, 64-thread
+    # headline run is reproducible: displacement-triggered search, 256-thread
     # force workgroups, cell edge = r_s
     main_scene = dict(scene, config=dict(scene["config"], rebuild_interval=0))
     results = {p: measure(args, p, main_scene, force_block=MAIN_FORCE_BLOCK, keep_state=True,

@@ -390,7 +390,7 @@ def test_drum_1m_forces_and_sets_after_steps(drum_pair):
 
 def test_drum_1m_settled_forces_one_step_both_precisions(Dem):
     """The state the headline benchmark times: the drum settled for 20,000
-    steps (dynamic search, 64-thread force workgroups), then one step of the
+    steps (dynamic search, 256-thread force workgroups), then one step of the
     GPU in each precision against the oracle from the same state.  The FP32
     law is held to the bar against the term scale (sum of the magnitudes of
     the spring and dashpot terms): at the end of a contact the dashpot pulls
@@ -398,7 +398,7 @@ def test_drum_1m_settled_forces_one_step_both_precisions(Dem):
     two large terms, each rounded to FP32."""
     sc = W.drum_scene()
     main = dict(sc, config=dict(sc["config"], rebuild_interval=0))
-    g = Dem.from_scene(main, precision="fp64", force_block=64)
+    g = Dem.from_scene(main, precision="fp64", force_block=256)
     for _ in range(4):
         g.step(5000)
     st = g.get_state()
