@@ -92,10 +92,12 @@ __global__ void k_keys(const InstDev* __restrict__ inst, StepParams sp,
                        uint32_t* __restrict__ keys, int* __restrict__ rank,
                        int* __restrict__ count, int* __restrict__ flags) {
   int i = xcd_block() * kBlock + threadIdx.x;
-  if (i >= sp.n) return;
-  int inf = info[i];
-  uint32_t key = sp.n_keys;
-  if (!(inf & kInactive)) {
+  // every lane stays to the end: the ranks are handed out per run of equal
+  // keys in the wavefront (below)
+  const bool valid = i < sp.n;
+  int inf = valid ? info[i] : kInactive;
+  uint32_t key = valid ? sp.n_keys : 0xffffffffu;
+  if (valid && !(inf & kInactive)) {
     const InstDev& I = inst[inf >> kInstShift];
     const GridDev& g = I.grid;
     double4 p = pos[i];
@@ -118,8 +120,25 @@ __global__ void k_keys(const InstDev* __restrict__ inst, StepParams sp,
       key = I.key_base + cell_key(g, cx, cy, cz);
     }
   }
-  keys[i] = key;
-  rank[i] = atomicAdd(&count[key], 1);
+  // Particles come in the previous search's spatial order, so lanes with the
+  // same cell mostly sit side by side: the first lane of each run of equal
+  // keys reserves the whole run with one atomic and hands consecutive ranks
+  // to the run (the order within a cell is fixed later by k_cell_rank).
+  const int lane = threadIdx.x & 63;
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  const bool first = lane == 0 || prev != key;
+  const unsigned long long starts = __builtin_amdgcn_ballot_w64(first);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const int lead = 63 - __builtin_clzll(starts & upto);
+  const unsigned long long after = lane == 63 ? 0ull : (starts & ~upto);
+  const int next = after ? __builtin_ctzll(after) : 64;
+  int base = 0;
+  if (first && valid) base = atomicAdd(&count[key], next - lane);
+  base = __shfl(base, lead, 64);
+  if (valid) {
+    keys[i] = key;
+    rank[i] = base + (lane - lead);
+  }
 }
 
 hipError_t launch_keys(const InstDev* inst, const StepParams& sp, const double4* pos,
