@@ -1257,9 +1257,16 @@ __device__ __forceinline__ double force_particle(
   // PAIRS 1: a single instance whose particles all have type 0, so every
   // pair takes the table's first entry, read once for the wavefront;
   // PAIRS 2: every particle has type 0, so the pair's entry is the first of
-  // the particle's own row and its load does not wait for the neighbour's
+  // the particle's own row (its load does not wait for the neighbour's
+  // type), read once for the wavefront when all its lanes share the row
   PairCoef pc0;
   if (PAIRS == 1) pc0 = ppc[0];
+  bool uni = false;  // PAIRS 2: the wavefront's lanes share one row
+  if (PAIRS == 2) {
+    const int rowu = __builtin_amdgcn_readfirstlane(row);
+    uni = __builtin_amdgcn_ballot_w64(row != rowu) == 0ull;
+    if (uni) pc0 = ppc[rowu];
+  }
   const double dt = sp.dt;
   double F[3] = {0.0, 0.0, 0.0};
   double T[3] = {0.0, 0.0, 0.0};
@@ -1297,7 +1304,10 @@ __device__ __forceinline__ double force_particle(
       if (PAIRS == 1) {
         pp_contact<R>(pc0, sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       } else if (PAIRS == 2) {
-        pp_contact<R>(ppi[0], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+        if (uni)
+          pp_contact<R>(pc0, sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
+        else
+          pp_contact<R>(ppi[0], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
       } else {
         const int tj = tile.info(info, j) & kTypeMask;
         pp_contact<R>(ppi[tj], sp.rolling, MODEL, dt, xi, vi, wi, xj, vj, wj, dtl, Fi, Mi);
