@@ -349,8 +349,8 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
                         move_forces ? c->F[p] : nullptr,
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
                         c->d_clock, step_rel, bound_step_rel, c->d_flags, s));
-  HIPCHK(launch_search(c->d_inst, (int)c->inst.size(), c->sp, c->pos[a ^ 1], c->info[p ^ 1], c->start, c->perm,
-                       c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
+  HIPCHK(launch_search(c->d_inst, (int)c->inst.size(), c->sp, c->pos[a ^ 1], c->info[p ^ 1],
+                       c->start, c->perm, c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
   c->pcur ^= 1;
   c->n_rebuilds += 1;
@@ -1025,7 +1025,8 @@ int commit(dem_ctx* c) {
   const int B = (int)c->inst.size();
   int64_t N = 0;
   for (const Instance& I : c->inst) N += I.n;
-  if (N > kMaxParticles) return set_err(DEM_EINVAL, "too many particles in the batch (at most 2^29)");
+  if (N > kMaxParticles)
+    return set_err(DEM_EINVAL, "too many particles in the batch (at most 2^29)");
   const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
   int64_t total_keys = 0;
   double bound_nb = 16.0;
