@@ -529,12 +529,12 @@ def main():
     ap.add_argument("--skip-silos", action="store_true", help="skip the two silo legs")
     ap.add_argument("--silo-fill", type=int, default=20000,
                     help="fill steps (of five times the run's time step) of the wedge silo")
-    ap.add_argument("--silo-steps", type=int, default=4000,
+    ap.add_argument("--silo-steps", type=int, default=20000,
                     help="timed discharge steps of the wedge silo")
     ap.add_argument("--hopper-fill", type=int, default=30000,
                     help="fill steps (of five times the run's time step) of the 4.3M-sphere "
                          "silo")
-    ap.add_argument("--hopper-steps", type=int, default=1000,
+    ap.add_argument("--hopper-steps", type=int, default=5000,
                     help="timed discharge steps of the 4.3M-sphere silo")
     ap.add_argument("--dam-n", type=int, default=1_280_000)
     ap.add_argument("--dam-steps", type=int, default=4000,
