@@ -142,10 +142,11 @@ def test_per_contact_and_normwise_force_errors(Dem, precision, tol):
     assert ce["max"] <= (1e-10 if precision == "fp64" else 1e-2)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32", FP32_TOL)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", FP32_TOL)])
 def test_forces_after_20_steps_dense(Dem, precision, tol):
     """After 20 steps (two searches) the states still agree closely and the
-    per-step forces stay within tolerance."""
+    per-step forces stay within the one-step bar (measured: FP64 7e-14, FP32
+    law 6.8e-6 on the torques)."""
     sc = W.dense_snapshot(n=2000, seed=2, K=10)
     g, o = make(Dem, sc, precision)
     g.step(20)
@@ -153,7 +154,7 @@ def test_forces_after_20_steps_dense(Dem, precision, tol):
     assert_same_contacts(g, o) if precision == "fp64" else None
     ef, et = force_err(g, o)
     print(precision, "force err after 20", ef, et, flush=True)
-    assert ef <= tol * 10 and et <= tol * 10
+    assert ef <= tol and et <= tol
 
 
 def test_euler_integrator_parity(Dem):

@@ -83,7 +83,10 @@ def test_small_silo_parity(Dem, kind, precision):
     ef, et = force_err(g, o, R)
     dx = np.max(np.abs(g.get_state()["pos"] - o.state()["pos"]))
     print(kind, precision, "step 20: err", ef, et, "max |dx|", dx, flush=True)
-    assert ef <= max(10 * tol, 1e-9) and et <= max(10 * tol, 1e-9)
+    # after 20 steps both precisions stay within the one-step bars (FP64
+    # measured 2e-12, FP32 law 2.3e-6 on the torques)
+    tol20 = 1e-10 if precision == "fp64" else 1e-5
+    assert ef <= tol20 and et <= tol20
     assert dx <= (1e-12 if precision == "fp64" else 1e-6 * 2e-3)
     # longer: the violent start makes the packing chaotic, so only the FP64
     # contact sets are compared (the outlet plug switches off at step 300)
