@@ -52,12 +52,18 @@
  *     velocity of body j, the wall's angular velocity enters the rolling term;
  *     restitution, friction and rolling friction are the wall material's;
  *   - unlike particle types: restitution, friction and rolling friction are the
- *     arithmetic means of the two materials;
+ *     arithmetic means of the two materials (parity unpinned: the paper fixes
+ *     no mixing rule and no closed form or published value checks this one;
+ *     the effective mass, radius and moduli of unlike spheres are pinned);
  *   - particles outside the domain box become inactive at a contact search;
  *   - viscous rolling torque against a wall: V_omega = R_i (omega_i -
  *     Omega_wall) x n (the particle's lever arm, spin relative to the wall's);
  *   - linear model: the tangential spring and damping constants equal the
  *     normal ones; e = 1 gives zero damping (the limit of the formula).
+ *
+ * Parity unpinned: trajectories of dense packings over long horizons, where
+ * the dynamics are chaotic; pins and comparisons use short horizons and
+ * non-chaotic scenes.
  */
 #include "oracle_dem.h"
 
