@@ -112,7 +112,7 @@ typedef struct {
   int32_t max_neighbors;   /* capacity per particle in use                  */
   int32_t precision;
   double r_s, cell_size, skin, d_max;  /* of instance 0 */
-  int64_t n_cells;         /* cell keys of the grid (Morton-padded)          */
+  int64_t n_cells;         /* cells of the grids (one key per cell)          */
   int64_t device_bytes;    /* device memory held by the context             */
 } dem_stats;
 

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "dem.h"
@@ -97,7 +98,7 @@ struct dem_ctx {
   size_t dev_bytes = 0;
   int force_block = kBlock;  // threads per force workgroup (64, 128, 256)
   double cell_factor = 0.0;  // cell edge / d_max of the grids in use
-  uint32_t* d_mort = nullptr;
+  uint32_t* d_ckey = nullptr;  // cell keys of every grid (GridDev::ckey)
   double4 *pos[2]{}, *vel[2]{}, *omg[2]{};
   int *gid[2]{}, *info[2]{};
   double4 *F[2]{}, *T[2]{};
@@ -228,7 +229,7 @@ void free_particles(dem_ctx* c) {
   c->allocs.clear();
   c->alloc_bytes.clear();
   c->dev_bytes = 0;
-  c->d_mort = nullptr;
+  c->d_ckey = nullptr;
   c->has_mesh = false;
   c->d_tri = nullptr;
   c->d_mcell = c->d_mcell_tri = nullptr;
@@ -875,22 +876,21 @@ double wall_rate(const dem_ctx* c) {
 }
 
 // Cell grid of every instance for the cell edge h = cf d_max (1 + 1e-9),
-// never below the search radius r_s: cell counts, Morton bit widths and one
-// key range per instance.  The instances keep their previous grids when the
-// new ones would not fit.
-int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* mort_total_out) {
+// never below the search radius r_s: cell counts and one key range per
+// instance.  The instances keep their previous grids when the new ones would
+// not fit.
+int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* ckey_total_out) {
   const int B = (int)c->inst.size();
   std::vector<GridDev> grids((size_t)B);
   std::vector<uint32_t> bases((size_t)B);
   std::vector<double> hs((size_t)B);
   int64_t total_keys = 0;
-  size_t mort_total = 0;
   for (int b = 0; b < B; ++b) {
     const Instance& I = c->inst[(size_t)b];
     const double h = std::max(cf * I.dmax * (1.0 + 1e-9), I.rs);
     GridDev g;
     memset(&g, 0, sizeof(g));
-    int bits_total = 0;
+    int64_t cells = 1;
     for (int k = 0; k < 3; ++k) {
       g.lo[k] = I.own_domain ? I.lo[k] : c->cfg.domain_lo[k];
       g.hi[k] = I.own_domain ? I.hi[k] : c->cfg.domain_hi[k];
@@ -898,17 +898,13 @@ int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* mort_tota
       const double cc = I.n > 0 ? ceil(span / h) : 1.0;
       if (!(cc < 1e6)) return set_err(DEM_EINVAL, "domain too large for the cell grid");
       g.nc[k] = std::max(1, (int)cc);
-      int bb = 0;
-      while ((1 << bb) < g.nc[k]) ++bb;
-      g.bits[k] = bb;
-      bits_total += bb;
-      mort_total += (size_t)g.nc[k];
+      cells *= g.nc[k];
     }
-    if (bits_total > 30)
+    if (cells >= ((int64_t)1 << 30))
       return set_err(DEM_EINVAL, "instance %d: cell grid %dx%dx%d is too large; shrink the domain",
                      b, g.nc[0], g.nc[1], g.nc[2]);
     g.h = I.n > 0 ? h : 1.0;
-    g.n_keys = (int64_t)1 << bits_total;
+    g.n_keys = cells;
     grids[(size_t)b] = g;
     hs[(size_t)b] = h;
     bases[(size_t)b] = (uint32_t)total_keys;
@@ -924,35 +920,58 @@ int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* mort_tota
   }
   c->cell_factor = cf;
   *total_keys_out = total_keys;
-  *mort_total_out = mort_total;
+  *ckey_total_out = (size_t)total_keys;
   return DEM_OK;
 }
 
-// Morton tables of the instance grids (bit b of axis a goes to the next free
-// key bit, taking levels b = 0, 1, ... and axes x, y, z in turn; the tables
-// live at c->d_mort) and the instance table.
-void grid_tables(dem_ctx* c, std::vector<uint32_t>* hmort, std::vector<InstDev>* hinst) {
+// Cell-key tables of the instance grids and the instance table.  A cell's
+// Morton code interleaves the bits of its coordinates (bit l of axis a goes
+// to the next free code bit, levels l = 0, 1, ... and axes x, y, z in turn,
+// an axis dropping out once its bits are used up); its key is its rank by
+// that code among the grid's cells.  The tables live at c->d_ckey.
+void grid_tables(dem_ctx* c, std::vector<uint32_t>* hckey, std::vector<InstDev>* hinst) {
   const int B = (int)c->inst.size();
-  hmort->clear();
+  hckey->clear();
   hinst->assign((size_t)B, InstDev{});
+  std::vector<std::pair<uint64_t, uint32_t>> code;
   for (int b = 0; b < B; ++b) {
     Instance& I = c->inst[(size_t)b];
     GridDev& g = I.grid;
+    int bits[3];
+    for (int a = 0; a < 3; ++a) {
+      bits[a] = 0;
+      while ((1 << bits[a]) < g.nc[a]) ++bits[a];
+    }
     int pos_of[3][32];
     int next = 0;
-    const int maxb = std::max(g.bits[0], std::max(g.bits[1], g.bits[2]));
+    const int maxb = std::max(bits[0], std::max(bits[1], bits[2]));
     for (int lvl = 0; lvl < maxb; ++lvl)
       for (int a = 0; a < 3; ++a)
-        if (lvl < g.bits[a]) pos_of[a][lvl] = next++;
+        if (lvl < bits[a]) pos_of[a][lvl] = next++;
+    std::vector<uint64_t> spread[3];
     for (int a = 0; a < 3; ++a) {
-      g.mort[a] = c->d_mort + hmort->size();
+      spread[a].resize((size_t)g.nc[a]);
       for (int ci = 0; ci < g.nc[a]; ++ci) {
-        uint32_t key = 0;
-        for (int lvl = 0; lvl < g.bits[a]; ++lvl)
-          if ((ci >> lvl) & 1) key |= 1u << pos_of[a][lvl];
-        hmort->push_back(key);
+        uint64_t m = 0;
+        for (int lvl = 0; lvl < bits[a]; ++lvl)
+          if ((ci >> lvl) & 1) m |= uint64_t(1) << pos_of[a][lvl];
+        spread[a][(size_t)ci] = m;
       }
     }
+    // (code, linear index) of every cell, x fastest; sorted by code they are
+    // in Morton order
+    const size_t base = hckey->size(), cells = (size_t)g.n_keys;
+    code.resize(cells);
+    size_t lin = 0;
+    for (int z = 0; z < g.nc[2]; ++z)
+      for (int y = 0; y < g.nc[1]; ++y)
+        for (int x = 0; x < g.nc[0]; ++x, ++lin)
+          code[lin] = {spread[0][(size_t)x] | spread[1][(size_t)y] | spread[2][(size_t)z],
+                       (uint32_t)lin};
+    std::sort(code.begin(), code.end());
+    hckey->resize(base + cells);
+    for (size_t r = 0; r < cells; ++r) (*hckey)[base + code[r].second] = (uint32_t)r;
+    g.ckey = c->d_ckey + base;
     InstDev& D = (*hinst)[(size_t)b];
     D.grid = g;
     D.key_base = I.key_base;
@@ -971,30 +990,30 @@ void grid_tables(dem_ctx* c, std::vector<uint32_t>* hmort, std::vector<InstDev>*
 // cells (histories are carried as at every search).
 int regrid(dem_ctx* c, double cf) {
   int64_t total_keys = 0;
-  size_t mort_total = 0;
-  int rc = plan_grids(c, cf, &total_keys, &mort_total);
+  size_t ckey_total = 0;
+  int rc = plan_grids(c, cf, &total_keys, &ckey_total);
   if (rc) return rc;
   destroy_graphs(c);
   HIPCHK(hipStreamSynchronize(c->stream));
   dfree(c, c->count);
   dfree(c, c->start);
   dfree(c, c->tile_sums);
-  dfree(c, c->d_mort);
+  dfree(c, c->d_ckey);
   c->count = c->start = c->tile_sums = nullptr;
-  c->d_mort = nullptr;
+  c->d_ckey = nullptr;
   rc = rc ? rc : dalloc_t(c, &c->count, (size_t)total_keys + 1);
   rc = rc ? rc : dalloc_t(c, &c->start, (size_t)total_keys + 2);
   rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((total_keys + 1 + 1023) / 1024 + 1));
-  rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_ckey, std::max<size_t>(ckey_total, 1));
   if (rc) {
     c->failed = true;
     return rc;
   }
-  std::vector<uint32_t> hmort;
+  std::vector<uint32_t> hckey;
   std::vector<InstDev> hinst;
-  grid_tables(c, &hmort, &hinst);
-  if (!hmort.empty())
-    HIPCHK(hipMemcpyAsync(c->d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
+  grid_tables(c, &hckey, &hinst);
+  if (!hckey.empty())
+    HIPCHK(hipMemcpyAsync(c->d_ckey, hckey.data(), hckey.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
                         hipMemcpyHostToDevice, c->stream));
@@ -1030,7 +1049,7 @@ int commit(dem_ctx* c) {
   const double f = std::min(c->cfg.neighbor_threshold, c->cfg.cell_factor);
   int64_t total_keys = 0;
   double bound_nb = 16.0;
-  size_t mort_total = 0;
+  size_t ckey_total = 0;
   int n_walls = 0;
   for (int b = 0; b < B; ++b) {
     Instance& I = c->inst[(size_t)b];
@@ -1053,7 +1072,7 @@ int commit(dem_ctx* c) {
     n_walls += (int)I.walls.size();
   }
   {
-    int rc = plan_grids(c, c->cfg.cell_factor, &total_keys, &mort_total);
+    int rc = plan_grids(c, c->cfg.cell_factor, &total_keys, &ckey_total);
     if (rc) return rc;
   }
   std::vector<TriDev> htri;
@@ -1146,7 +1165,7 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_flags, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
-  rc = rc ? rc : dalloc_t(c, &c->d_mort, std::max<size_t>(mort_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_ckey, std::max<size_t>(ckey_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
   rc = rc ? rc : dalloc_t(c, &c->d_bacc, 3);
   rc = rc ? rc : dalloc_t(c, &c->d_brec, 3 * (size_t)kDriftSpread);
@@ -1178,10 +1197,10 @@ int commit(dem_ctx* c) {
     return rc;
   }
 
-  // Morton tables, instance table, walls and material-pair tables
-  std::vector<uint32_t> hmort;
+  // cell-key tables, instance table, walls and material-pair tables
+  std::vector<uint32_t> hckey;
   std::vector<InstDev> hinst;
-  grid_tables(c, &hmort, &hinst);
+  grid_tables(c, &hckey, &hinst);
   std::vector<WallDev> hwalls;
   std::vector<PairCoef> pp((size_t)B * kMaxTypes * kMaxTypes), pw(pp.size());
   memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
@@ -1240,8 +1259,8 @@ int commit(dem_ctx* c) {
   }
   hipStream_t s = c->stream;
   if ((rc = wait_user(c))) return rc;
-  if (!hmort.empty())
-    HIPCHK(hipMemcpyAsync(c->d_mort, hmort.data(), hmort.size() * sizeof(uint32_t),
+  if (!hckey.empty())
+    HIPCHK(hipMemcpyAsync(c->d_ckey, hckey.data(), hckey.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
                         hipMemcpyHostToDevice, s));

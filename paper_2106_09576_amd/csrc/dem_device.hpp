@@ -101,16 +101,16 @@ struct MeshTables {
 };
 
 // Uniform cell grid of one instance: cell (cx,cy,cz) = floor((x - lo)/h).
-// Cells are ordered along a Morton (Z-order) curve:
-// key = mort[0][cx] | mort[1][cy] | mort[2][cz], where mort[a] spreads the
-// bits of a coordinate into its interleaved key positions (axes with fewer
-// bits drop out of the interleave at the top).
+// Cells are ordered along a Morton (Z-order) curve (the bits of the three
+// coordinates interleaved; axes with fewer bits drop out of the interleave at
+// the top), and a cell's key is its rank in that order among the grid's
+// cells: key = ckey[(cz * nc[1] + cy) * nc[0] + cx], 0 .. n_keys - 1, so the
+// key space has no unused keys (a power-of-two Morton range would).
 struct GridDev {
   double lo[3], hi[3], h;
   int nc[3];
-  int bits[3];
-  const uint32_t* mort[3];
-  int64_t n_keys;  // 2^(bits0 + bits1 + bits2)
+  const uint32_t* ckey;
+  int64_t n_keys;  // nc[0] * nc[1] * nc[2]
 };
 
 // One independent simulation of a batch.  Its cells use the global keys

@@ -53,7 +53,7 @@ __device__ inline int cell_coord(double x, double lo, double h, int nc) {
 }
 
 __device__ inline uint32_t cell_key(const GridDev& g, int cx, int cy, int cz) {
-  return g.mort[0][cx] | g.mort[1][cy] | g.mort[2][cz];
+  return g.ckey[(cz * g.nc[1] + cy) * g.nc[0] + cx];  // fewer than 2^30 cells
 }
 
 // Slot of the displacement-bound ring (StepParams) for absolute step s + d
@@ -188,16 +188,24 @@ __global__ void k_scan_tiles(const int* __restrict__ in, int64_t m, int* __restr
   if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
+// One workgroup: thread t takes the contiguous chunk [t c, (t + 1) c) of the
+// nt tile sums (c = ceil(nt / kBlock)), adds it up (independent loads, not
+// one dependent round per kBlock sums), the chunk totals are scanned across
+// the workgroup, and each thread writes its chunk's exclusive prefixes.
 __global__ void k_scan_sums(int* __restrict__ tsum, int64_t nt) {
   __shared__ int sh[4];
-  int carry = 0;
-  for (int64_t base = 0; base < nt; base += kBlock) {
-    int64_t i = base + threadIdx.x;
-    int v = i < nt ? tsum[i] : 0;
-    int tot;
-    int ex = block_exclusive_scan(v, sh, &tot);
-    if (i < nt) tsum[i] = ex + carry;
-    carry += tot;
+  const int64_t c = (nt + kBlock - 1) / kBlock;
+  const int64_t a = (int64_t)threadIdx.x * c;
+  const int64_t b = a + c < nt ? a + c : nt;
+  int s = 0;
+#pragma unroll 8
+  for (int64_t i = a; i < b; ++i) s += tsum[i];
+  int tot;
+  int ex = block_exclusive_scan(s, sh, &tot);
+  for (int64_t i = a; i < b; ++i) {
+    const int v = tsum[i];
+    tsum[i] = ex;
+    ex += v;
   }
 }
 
@@ -713,9 +721,11 @@ __device__ __forceinline__ void place_class(const BuildRow& row, Five& nx, const
 }
 
 // kOne: the batch has a single instance, whose table entry then sits in
-// scalar registers.
+// scalar registers.  Eight wavefronts per SIMD (at most 64 VGPRs; both
+// instantiations fit without spills): the scan is bound by the latency of
+// its candidate loads.
 template <bool kOne>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 k_search(const InstDev* __restrict__ inst, StepParams sp,
                          const double4* __restrict__ pos,
                          const int* __restrict__ info, const int* __restrict__ start,
@@ -754,11 +764,12 @@ k_search(const InstDev* __restrict__ inst, StepParams sp,
     for (int dy = -1; dy <= 1; ++dy) {
       const int y = cy + dy;
       if (y < 0 || y >= g.nc[1]) continue;
-      const uint32_t kyz = g.mort[1][y] | g.mort[2][z];
+      // (fewer than 2^30 cells: the index fits an int)
+      const uint32_t* krow = g.ckey + (z * g.nc[1] + y) * g.nc[0];
       for (int dx = -1; dx <= 1; ++dx) {
         const int x = cx + dx;
         if (x < 0 || x >= g.nc[0]) continue;
-        const uint32_t key = kbase + (g.mort[0][x] | kyz);
+        const uint32_t key = kbase + krow[x];
         const int s = start[key], e = start[key + 1];
         for (int q = s; q < e; ++q) {
           if (q == p) continue;
