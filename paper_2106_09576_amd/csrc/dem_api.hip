@@ -99,6 +99,8 @@ struct dem_ctx {
   int force_block = kBlock;  // threads per force workgroup (64, 128, 256)
   double cell_factor = 0.0;  // cell edge / d_max of the grids in use
   uint32_t* d_ckey = nullptr;  // cell keys of every grid (GridDev::ckey)
+  uint32_t* d_key_cell = nullptr;  // inverse: the cell (key_base + position) of each key
+  int2* d_cse = nullptr;  // (start, end) of each cell at its position, written by the scan
   double4 *pos[2]{}, *vel[2]{}, *omg[2]{};
   int *gid[2]{}, *info[2]{};
   double4 *F[2]{}, *T[2]{};
@@ -230,6 +232,8 @@ void free_particles(dem_ctx* c) {
   c->alloc_bytes.clear();
   c->dev_bytes = 0;
   c->d_ckey = nullptr;
+  c->d_key_cell = nullptr;
+  c->d_cse = nullptr;
   c->has_mesh = false;
   c->d_tri = nullptr;
   c->d_mcell = c->d_mcell_tri = nullptr;
@@ -338,7 +342,8 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
   HIPCHK(launch_fill_i32(c->count, 0, c->n_keys + 1, s));
   HIPCHK(launch_keys(c->d_inst, c->sp, c->pos[a], c->vel[a], c->info[p], c->xref, check_guard,
                      c->keys, c->rank, c->count, c->d_flags, s));
-  HIPCHK(launch_scan(c->count, c->start, c->n_keys + 1, c->tile_sums, s));
+  HIPCHK(launch_scan(c->count, c->start, c->n_keys + 1, c->tile_sums, s, c->d_key_cell, c->d_cse,
+                     c->n_keys));
   HIPCHK(launch_scatter(c->n, c->keys, c->rank, c->start, c->perm0, s));
   HIPCHK(launch_cell_rank(c->n, c->n_keys, c->perm0, c->keys, c->start, c->gid[p],
                           c->perm, s));
@@ -351,7 +356,7 @@ int enqueue_rebuild(dem_ctx* c, int check_guard, int move_forces, int64_t step_r
                         move_forces ? c->T[p] : nullptr, c->F[p ^ 1], c->T[p ^ 1],
                         c->d_clock, step_rel, bound_step_rel, c->d_flags, s));
   HIPCHK(launch_search(c->d_inst, (int)c->inst.size(), c->sp, c->pos[a ^ 1], c->info[p ^ 1],
-                       c->start, c->perm, c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
+                       c->d_cse, c->perm, c->inv, nlist(c, p), nlist(c, p ^ 1), c->d_flags, s));
   c->cur ^= 1;
   c->pcur ^= 1;
   c->n_rebuilds += 1;
@@ -928,10 +933,13 @@ int plan_grids(dem_ctx* c, double cf, int64_t* total_keys_out, size_t* ckey_tota
 // Morton code interleaves the bits of its coordinates (bit l of axis a goes
 // to the next free code bit, levels l = 0, 1, ... and axes x, y, z in turn,
 // an axis dropping out once its bits are used up); its key is its rank by
-// that code among the grid's cells.  The tables live at c->d_ckey.
-void grid_tables(dem_ctx* c, std::vector<uint32_t>* hckey, std::vector<InstDev>* hinst) {
+// that code among the grid's cells.  The tables live at c->d_ckey; hkeycell
+// (at c->d_key_cell) is the inverse, key -> cell, both over all instances.
+void grid_tables(dem_ctx* c, std::vector<uint32_t>* hckey, std::vector<uint32_t>* hkeycell,
+                 std::vector<InstDev>* hinst) {
   const int B = (int)c->inst.size();
   hckey->clear();
+  hkeycell->clear();
   hinst->assign((size_t)B, InstDev{});
   std::vector<std::pair<uint64_t, uint32_t>> code;
   for (int b = 0; b < B; ++b) {
@@ -970,7 +978,11 @@ void grid_tables(dem_ctx* c, std::vector<uint32_t>* hckey, std::vector<InstDev>*
                        (uint32_t)lin};
     std::sort(code.begin(), code.end());
     hckey->resize(base + cells);
-    for (size_t r = 0; r < cells; ++r) (*hckey)[base + code[r].second] = (uint32_t)r;
+    hkeycell->resize(base + cells);
+    for (size_t r = 0; r < cells; ++r) {
+      (*hckey)[base + code[r].second] = (uint32_t)r;
+      (*hkeycell)[base + r] = (uint32_t)(base + code[r].second);
+    }
     g.ckey = c->d_ckey + base;
     InstDev& D = (*hinst)[(size_t)b];
     D.grid = g;
@@ -999,22 +1011,30 @@ int regrid(dem_ctx* c, double cf) {
   dfree(c, c->start);
   dfree(c, c->tile_sums);
   dfree(c, c->d_ckey);
+  dfree(c, c->d_key_cell);
+  dfree(c, c->d_cse);
   c->count = c->start = c->tile_sums = nullptr;
-  c->d_ckey = nullptr;
+  c->d_ckey = c->d_key_cell = nullptr;
+  c->d_cse = nullptr;
   rc = rc ? rc : dalloc_t(c, &c->count, (size_t)total_keys + 1);
   rc = rc ? rc : dalloc_t(c, &c->start, (size_t)total_keys + 2);
   rc = rc ? rc : dalloc_t(c, &c->tile_sums, (size_t)((total_keys + 1 + 1023) / 1024 + 1));
   rc = rc ? rc : dalloc_t(c, &c->d_ckey, std::max<size_t>(ckey_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_key_cell, std::max<size_t>(ckey_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_cse, std::max<size_t>(ckey_total, 1));
   if (rc) {
     c->failed = true;
     return rc;
   }
-  std::vector<uint32_t> hckey;
+  std::vector<uint32_t> hckey, hkeycell;
   std::vector<InstDev> hinst;
-  grid_tables(c, &hckey, &hinst);
-  if (!hckey.empty())
+  grid_tables(c, &hckey, &hkeycell, &hinst);
+  if (!hckey.empty()) {
     HIPCHK(hipMemcpyAsync(c->d_ckey, hckey.data(), hckey.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_key_cell, hkeycell.data(), hkeycell.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, c->stream));
+  }
   HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
                         hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1166,6 +1186,8 @@ int commit(dem_ctx* c) {
   rc = rc ? rc : dalloc_t(c, &c->d_clock, 1);
   rc = rc ? rc : dalloc_t(c, &c->d_stats, 4);
   rc = rc ? rc : dalloc_t(c, &c->d_ckey, std::max<size_t>(ckey_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_key_cell, std::max<size_t>(ckey_total, 1));
+  rc = rc ? rc : dalloc_t(c, &c->d_cse, std::max<size_t>(ckey_total, 1));
   rc = rc ? rc : dalloc_t(c, &c->d_drift, (size_t)kDriftSpread * (kDynChunk + 1));
   rc = rc ? rc : dalloc_t(c, &c->d_bacc, 3);
   rc = rc ? rc : dalloc_t(c, &c->d_brec, 3 * (size_t)kDriftSpread);
@@ -1198,9 +1220,9 @@ int commit(dem_ctx* c) {
   }
 
   // cell-key tables, instance table, walls and material-pair tables
-  std::vector<uint32_t> hckey;
+  std::vector<uint32_t> hckey, hkeycell;
   std::vector<InstDev> hinst;
-  grid_tables(c, &hckey, &hinst);
+  grid_tables(c, &hckey, &hkeycell, &hinst);
   std::vector<WallDev> hwalls;
   std::vector<PairCoef> pp((size_t)B * kMaxTypes * kMaxTypes), pw(pp.size());
   memset(pp.data(), 0, pp.size() * sizeof(PairCoef));
@@ -1259,9 +1281,12 @@ int commit(dem_ctx* c) {
   }
   hipStream_t s = c->stream;
   if ((rc = wait_user(c))) return rc;
-  if (!hckey.empty())
+  if (!hckey.empty()) {
     HIPCHK(hipMemcpyAsync(c->d_ckey, hckey.data(), hckey.size() * sizeof(uint32_t),
                           hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->d_key_cell, hkeycell.data(), hkeycell.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipMemcpyAsync(c->d_inst, hinst.data(), hinst.size() * sizeof(InstDev),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->d_pp, pp.data(), pp.size() * sizeof(PairCoef), hipMemcpyHostToDevice, s));

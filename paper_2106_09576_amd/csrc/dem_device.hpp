@@ -201,9 +201,11 @@ hipError_t launch_fill_i32(int* p, int v, int64_t n, hipStream_t s);
 hipError_t launch_keys(const InstDev* inst, const StepParams& sp, const double4* pos,
                        const double4* vel, int* info, const double4* xref, int check_guard,
                        uint32_t* keys, int* rank, int* count, int* flags, hipStream_t s);
-// exclusive scan of count[0..m) into start[0..m], start[m] = total
-hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums,
-                       hipStream_t s);
+// exclusive scan of count[0..m) into start[0..m], start[m] = total; with cse
+// also cse[key_cell[k]] = (start[k], start[k + 1]) for the keys k < n_cells
+hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums, hipStream_t s,
+                       const uint32_t* key_cell = nullptr, int2* cse = nullptr,
+                       int64_t n_cells = 0);
 hipError_t launch_scatter(int n, const uint32_t* keys, const int* rank, const int* start,
                           int* perm0, hipStream_t s);
 hipError_t launch_cell_rank(int n, int64_t n_keys, const int* perm0, const uint32_t* keys,
@@ -222,8 +224,10 @@ hipError_t launch_reorder(const StepParams& sp, const InstDev* inst, const int* 
                           const double4* F_src, const double4* T_src, double4* F_dst,
                           double4* T_dst, const int64_t* clock, int64_t step_rel,
                           int64_t bound_step_rel, int* flags, hipStream_t s);
+// cse: (start, end) of every cell in sorted order, indexed by the cell's
+// position (key_base + (cz * nc[1] + cy) * nc[0] + cx)
 hipError_t launch_search(const InstDev* inst, int n_inst, const StepParams& sp,
-                         const double4* pos, const int* info, const int* start, const int* perm,
+                         const double4* pos, const int* info, const int2* cse, const int* perm,
                          const int* inv, NbrList old_l, NbrList new_l, int* flags,
                          hipStream_t s);
 

@@ -209,8 +209,11 @@ __global__ void k_scan_sums(int* __restrict__ tsum, int64_t nt) {
   }
 }
 
+// With cse: also the (start, end) pair of each of the first n_cells keys,
+// stored at that key's cell (key_cell), for lookups by cell position.
 __global__ void k_scan_apply(const int* __restrict__ in, int64_t m, const int* __restrict__ tsum,
-                             int* __restrict__ out) {
+                             int* __restrict__ out, const uint32_t* __restrict__ key_cell,
+                             int2* __restrict__ cse, int64_t n_cells) {
   __shared__ int sh[4];
   int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
   int v[4];
@@ -225,20 +228,21 @@ __global__ void k_scan_apply(const int* __restrict__ in, int64_t m, const int* _
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (base + k < m) out[base + k] = ex;
+    if (cse && base + k < n_cells) cse[key_cell[base + k]] = make_int2(ex, ex + v[k]);
     ex += v[k];
   }
   // the element after the last one holds the total
   if (base <= m - 1 && m - 1 < base + 4) out[m] = ex;
 }
 
-hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums,
-                       hipStream_t s) {
+hipError_t launch_scan(const int* count, int* start, int64_t m, int* tile_sums, hipStream_t s,
+                       const uint32_t* key_cell, int2* cse, int64_t n_cells) {
   if (m <= 0) return hipSuccess;
   int64_t nt = (m + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(kBlock), 0, s, count, m, tile_sums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, tile_sums, nt);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kBlock), 0, s, count, m, tile_sums,
-                     start);
+                     start, key_cell, cse, n_cells);
   return hipGetLastError();
 }
 
@@ -728,7 +732,7 @@ template <bool kOne>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 k_search(const InstDev* __restrict__ inst, StepParams sp,
                          const double4* __restrict__ pos,
-                         const int* __restrict__ info, const int* __restrict__ start,
+                         const int* __restrict__ info, const int2* __restrict__ cse,
                          const int* __restrict__ perm, const int* __restrict__ inv,
                          NbrList old_l, NbrList new_l, int* __restrict__ flags) {
   const int b0 = xcd_block() * kBlock;
@@ -764,13 +768,14 @@ k_search(const InstDev* __restrict__ inst, StepParams sp,
     for (int dy = -1; dy <= 1; ++dy) {
       const int y = cy + dy;
       if (y < 0 || y >= g.nc[1]) continue;
+      // the cells of row (y, z), each with its (start, end) in sorted order
       // (fewer than 2^30 cells: the index fits an int)
-      const uint32_t* krow = g.ckey + (z * g.nc[1] + y) * g.nc[0];
+      const int2* crow = cse + kbase + (z * g.nc[1] + y) * g.nc[0];
       for (int dx = -1; dx <= 1; ++dx) {
         const int x = cx + dx;
         if (x < 0 || x >= g.nc[0]) continue;
-        const uint32_t key = kbase + krow[x];
-        const int s = start[key], e = start[key + 1];
+        const int2 se = crow[x];
+        const int s = se.x, e = se.y;
         for (int q = s; q < e; ++q) {
           if (q == p) continue;
           const double4 pq = tile.get(pos, q);
@@ -874,16 +879,16 @@ k_search(const InstDev* __restrict__ inst, StepParams sp,
 }
 
 hipError_t launch_search(const InstDev* inst, int n_inst, const StepParams& sp,
-                         const double4* pos, const int* info, const int* start, const int* perm,
+                         const double4* pos, const int* info, const int2* cse, const int* perm,
                          const int* inv, NbrList old_l, NbrList new_l, int* flags,
                          hipStream_t s) {
   if (sp.n <= 0) return hipSuccess;
   if (n_inst == 1)
     hipLaunchKernelGGL(k_search<true>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos,
-                       info, start, perm, inv, old_l, new_l, flags);
+                       info, cse, perm, inv, old_l, new_l, flags);
   else
     hipLaunchKernelGGL(k_search<false>, dim3(grid_for(sp.n)), dim3(kBlock), 0, s, inst, sp, pos,
-                       info, start, perm, inv, old_l, new_l, flags);
+                       info, cse, perm, inv, old_l, new_l, flags);
   return hipGetLastError();
 }
 
